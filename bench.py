@@ -1,0 +1,143 @@
+"""Benchmark: two-dot DMRG sigma = H psi on one MI355X.
+
+A step is one sigma call over the whole two-dot problem (all operator
+families, R-step and L-step GEMMs with the fused reduction), FP64, with the
+operators and psi already resident in HBM.  Default workload: K=73, N=114
+(57 alpha, 57 beta), Sz=0, D=2000, two dots at the middle of the chain
+(sites 36, 37 counting from 1), seeded synthetic integrals and MPS.
+
+Prints one JSON line (see the design doc for every field).
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H·ψ sigma TFLOP/s & ms/call (K=73, D=2000); Davidson time to 1e-6 Eh"
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+
+CONFIGS = {
+    # name: (K, N_alpha, N_beta, D, bond, seed)
+    "1": (8, 4, 4, 64, 3, 1),
+    "2": (24, 12, 12, 1000, 11, 2),
+    "3": (36, 18, 18, 3000, 17, 3),
+    "5": (73, 57, 57, 2000, 35, 5),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ctx):
+    """The oracle (O1) timed on the host on a bounded sample of the workload."""
+    import synth
+    from oracle import blocks
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    K, Na, Nb, D, k, seed = 12, 6, 6, 200, 5, 6
+    ints = synth.make_integrals(K, 1000 + seed)
+    mps = synth.make_mps(K, Na, Nb, D, k, 3000 + seed)
+    psi = synth.make_psi(mps, 2000 + seed)
+    flops = ctx.build_ops(ints, mps).stats()["flops_sigma"]
+    t0 = time.time()
+    ob = blocks.TwoDotBlocks(ints, mps)
+    t_build = time.time() - t0
+    ts = []
+    for _ in range(3):
+        t0 = time.time()
+        ob.sigma(psi)
+        ts.append(time.time() - t0)
+    t = float(np.median(ts))
+    return {"value": flops / t / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle O1 sigma (dense super-block bipartition) on a K={K}, N={Na + Nb}, D={D} "
+                       f"two-dot at sites ({k},{k + 1}) of the same synthetic family; median of 3 calls "
+                       f"= {t * 1e3:.1f} ms/call; rate = the GPU plan's {flops / 1e9:.3f} GFLOP per call "
+                       f"of that sample / oracle time; oracle operator build {t_build:.1f} s excluded")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="5", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU operator-parallel "
+              f"path is a design in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2311_02854_amd import gpu_context
+
+    K, Na, Nb, D, k, seed = CONFIGS[args.config]
+    log(f"[bench] config {args.config}: K={K} N=({Na},{Nb}) D={D} bond={k}")
+    t0 = time.time()
+    ints = synth.make_integrals(K, 1000 + seed)
+    mps = synth.make_mps(K, Na, Nb, D, k, 3000 + seed)
+    psi = synth.make_psi(mps, 2000 + seed)
+    log(f"[bench] synthetic inputs {time.time() - t0:.1f} s, n_psi={len(psi)}")
+    ctx = gpu_context(0)
+    t0 = time.time()
+    ops = ctx.build_ops(ints, mps)
+    t_build = time.time() - t0
+    st = ops.stats()
+    log(f"[bench] build_ops {t_build:.1f} s ({st['build_flops'] / 1e12:.1f} TFLOP renormalization), "
+        f"sigma plan {st['flops_sigma'] / 1e12:.3f} TFLOP/call, ops {st['op_bytes'] / 1e9:.1f} GB")
+    x = torch.from_numpy(psi).cuda()
+    y = torch.empty_like(x)
+    for i in range(args.warmup):
+        ops.sigma(x.data_ptr(), y.data_ptr())
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    ops.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ops.sigma(x.data_ptr(), y.data_ptr())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = ops.stats()
+    ops.profile(False)
+    ms = dt / args.steps * 1e3
+    flops = st["flops_sigma"]
+    tflops = flops / (dt / args.steps) / 1e12
+    kern_ms = (prof["prof_rstep_ms"] + prof["prof_lstep_ms"]) / max(1, prof["prof_sigma_calls"])
+    achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
+    log(f"[bench] {args.steps} steps: {ms:.1f} ms/call, {tflops:.2f} TFLOP/s; GEMM kernels {kern_ms:.1f} ms/call")
+    out = {
+        "metric": METRIC, "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"two-dot DMRG sigma, K={K}, N={Na + Nb} ({Na}a,{Nb}b), Sz=0, D={D}, "
+                                f"dots at sites ({k + 1},{k + 2}) of 1..K, seeded integrals and MPS"),
+                   "n_psi": int(st["n_psi"]), "psi_blocks": int(st["n_blocks"]), "terms": int(st["n_terms"]),
+                   "gemms_per_call": int(st["n_rgemm"] + st["n_lgemm"]), "tflop_per_call": flops / 1e12,
+                   "build_ops_s": t_build, "operator_GB": st["op_bytes"] / 1e9},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None, "traffic": None,
+                     "kernel": "gemm_f64_kernel", "kernel_ms_per_call": kern_ms,
+                     "launches_per_call": prof["prof_launches"] / max(1, prof["prof_sigma_calls"])},
+    }
+    if not args.no_cpu:
+        log("[bench] cpu_baseline: oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

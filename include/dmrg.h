@@ -1,0 +1,182 @@
+/*
+ * dmrg.h -- C ABI of the MI355X two-site DMRG sigma-vector engine.
+ *
+ * The library computes, for one bond of an ab initio DMRG sweep, the Davidson
+ * sigma-vector sigma = H psi of the two-dot problem (paper, Sec. 2.1, Eq. Sigma;
+ * Hamiltonian Eq. Hsq, sum-of-products form Eq. totoalH), its diagonal, and
+ * the lowest eigenpair by Davidson's method.  The renormalized block
+ * operators (the qops set, Sec. 2.3, Eq. qops) are built on the GPU from the
+ * integrals and a U(1)xU(1) block-sparse MPS (Eq. MPS, Eq. Renorm).
+ *
+ * Conventions
+ *   - Spatial orbitals 0..K-1, one per site, in MPS order.  Spin orbital
+ *     p = 2*i + s (s = 0 alpha, 1 beta); Jordan-Wigner order is site by site,
+ *     alpha before beta.  Site basis n = 0..3 is {|vac>, |beta>, |alpha>,
+ *     |alpha beta>} (Sec. 2.1) with |alpha beta> = a+_alpha a+_beta |vac>.
+ *   - Bond b (0..K) lies between sites b-1 and b.  A sector at bond b is
+ *     labelled by (q_alpha, q_beta), the electron numbers of sites 0..b-1.
+ *   - All functions return 0 on success or a negative dmrg_status; nothing
+ *     throws across the ABI.  dmrg_last_error() gives a message.
+ *   - All floating point data are IEEE binary64 unless stated otherwise.
+ *   - Every entry point that takes a context issues its GPU work on the
+ *     context's HIP stream, in call order.  Calls that share a context must
+ *     not run concurrently from several host threads.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DMRG_OK = 0,
+  DMRG_EINVAL = -1,   /* bad argument (null pointer, out-of-range value) */
+  DMRG_ESHAPE = -2,   /* inconsistent sectors / MPS blocks / empty two-dot space */
+  DMRG_ENOMEM = -3,   /* device or host allocation failed */
+  DMRG_EHIP = -4,     /* a HIP runtime call or kernel launch failed */
+  DMRG_ENOCONV = -5,  /* Davidson reached max_iter; the best pair is still returned */
+  DMRG_EINTERNAL = -6
+} dmrg_status;
+
+typedef enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16X3 = 2 } dmrg_precision;
+
+typedef struct dmrg_ctx dmrg_ctx;  /* device, stream, last error */
+typedef struct dmrg_ops dmrg_ops;  /* renormalized operators + sigma plan of one bond (device) */
+
+/* Integrals of Eq. (Hsq) in spatial orbitals (host memory, read during the call,
+ * never retained):
+ *   h[K*K]       one-electron h_pq, row-major, symmetric
+ *   eri[K^4]     two-electron (pq|rs) in chemist notation, index ((p*K+q)*K+r)*K+s,
+ *                with the 8-fold permutational symmetry of real orbitals
+ *   ecore        constant added to H (enters sigma as ecore*psi). */
+typedef struct {
+  int K;
+  const double* h;
+  const double* eri;
+  double ecore;
+} dmrg_integrals;
+
+/* Block-sparse MPS (Eq. MPS) under U(1)xU(1) (host memory, copied):
+ *   K, n_alpha, n_beta   orbitals and target electron numbers
+ *   bond                 the two dots are sites (bond, bond+1), 0 <= bond <= K-2
+ *   nsec[K+1]            number of sectors at each bond
+ *   sec_qn[2*S]          (q_alpha, q_beta) of every sector, bonds in order, S = sum nsec
+ *   sec_dim[S]           sector dimensions (> 0)
+ *   blk_off[B]           element offset into data of every site-tensor block
+ *   data                 site tensors A[j] for j < bond (left-canonical) and
+ *                        j > bond+1 (right-canonical), sites ascending.  The blocks
+ *                        of A[j] are (il, n, ir) with il a sector of bond j, n a site
+ *                        state, ir the sector of bond j+1 with q(ir) = q(il) + q(n);
+ *                        enumerated by il ascending then n ascending, each a dense
+ *                        d_il x d_ir row-major array.  B counts all such blocks. */
+typedef struct {
+  int K, n_alpha, n_beta, bond;
+  const int* nsec;
+  const int* sec_qn;
+  const int* sec_dim;
+  const int64_t* blk_off;
+  const double* data;
+} dmrg_mps;
+
+/* Work statistics of one bond's plan (filled by dmrg_ops_stats). */
+typedef struct {
+  int64_t n_psi;          /* length of psi / sigma */
+  int64_t n_blocks;       /* psi blocks */
+  int64_t n_terms;        /* operator-pair families x members (terms mu of Eq. totoalH) */
+  int64_t n_rgemm;        /* GEMMs of the right-operator step (Eq. sigmablk56) */
+  int64_t n_lgemm;        /* GEMMs of the left-operator step (Eq. sigmablk78) */
+  double flops_sigma;     /* sum 2MNK over all GEMMs of one sigma call */
+  double flops_rstep;     /* the part in the right-operator step */
+  double flops_lstep;     /* the part in the left-operator step */
+  double op_bytes;        /* device bytes of operators kept for sigma */
+  double build_seconds;   /* wall time of dmrg_build_ops */
+  double build_flops;     /* sum 2MNK of the renormalization GEMMs */
+  /* live kernel timing since the last dmrg_profile(ops, 1): HIP events recorded
+   * on the context stream around every GEMM launch of dmrg_sigma (FP64) */
+  int64_t prof_sigma_calls;
+  int64_t prof_launches;
+  double prof_rstep_ms;   /* summed duration of the right-operator launches */
+  double prof_lstep_ms;   /* summed duration of the left-operator launches */
+} dmrg_stats;
+
+/* Davidson options (paper Sec. 2.1 names Davidson's method; details are ours). */
+typedef struct {
+  double tol_residual;     /* stop when ||H x - theta x||_2 <= tol_residual (default 1e-6) */
+  int max_iter;            /* sigma calls, default 200 */
+  int m_max;               /* subspace size before restart, 4..32, default 24 */
+  int precision;           /* dmrg_precision of sigma in early iterations */
+  double switch_residual;  /* reduced precision used while ||r|| > switch_residual */
+  int precond;             /* 0 diagonal, 1 learned MLP (falls back to diagonal) */
+  const float* mlp_weights;/* host weights for precond == 1, layout in dmrg_mlp_size */
+  double e_ref;            /* if finite: record time/iterations to reach e_ref + e_tol */
+  double e_tol;
+} dmrg_davidson_opts;
+
+typedef struct {
+  int iterations;          /* sigma calls made */
+  int sigma_fp64;          /* of which in FP64 */
+  double residual;         /* final ||r||_2 */
+  double seconds;          /* wall time of the call */
+  double seconds_to_ref;   /* time to first Ritz value <= e_ref + e_tol (or -1) */
+  int iters_to_ref;
+  int mlp_fallbacks;       /* iterations where the MLP correction was rejected */
+} dmrg_davidson_stats;
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t, may be NULL for the default stream). */
+int dmrg_create(dmrg_ctx** ctx, int device, void* hip_stream);
+void dmrg_destroy(dmrg_ctx* ctx);
+const char* dmrg_last_error(const dmrg_ctx* ctx);
+
+/* Build the renormalized operators of the two-dot problem at mps->bond by
+ * growing the left block over sites 0..bond-1 and the right block over sites
+ * K-1..bond+2 (Eq. Renorm on the GPU), then form the complementary operators
+ * and intermediates and plan sigma.  Synchronous.  *out is owned by the caller
+ * and released with dmrg_ops_destroy. */
+int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mps,
+                   dmrg_ops** out);
+void dmrg_ops_destroy(dmrg_ops* ops);
+
+/* psi layout: blocks (il, n1, n2, ir), il a sector of bond `bond`, ir the sector
+ * of bond `bond+2` with q(ir) = q(il) + q(n1) + q(n2), enumerated by (il, n1, n2);
+ * each block d_il x d_ir row-major.  blk_meta[6*nb] = (il, n1, n2, ir, d_il, d_ir),
+ * blk_off[nb] = element offsets.  Either array may be NULL. */
+int dmrg_ops_layout(const dmrg_ops* ops, int64_t* n_psi, int64_t* n_blocks,
+                    int* blk_meta, int64_t* blk_off);
+int dmrg_ops_stats(const dmrg_ops* ops, dmrg_stats* st);
+
+/* Enable (1) or disable (0) per-launch kernel timing of dmrg_sigma and reset
+ * its counters.  While enabled every dmrg_sigma call synchronises the context
+ * stream once at its end to read the events. */
+int dmrg_profile(dmrg_ops* ops, int enable);
+
+/* sigma = H psi (Eq. Sigma), psi and sigma device pointers of n_psi elements.
+ * precision DMRG_FP64: binary64 in and out.  DMRG_FP32 / DMRG_BF16X3: psi and
+ * sigma are still binary64 buffers; the contraction runs in reduced precision
+ * with FP32 accumulation.  Asynchronous on the context stream.  psi and sigma
+ * must not overlap. */
+int dmrg_sigma(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi, double* sigma,
+               int precision);
+
+/* Diagonal H_ii of the two-dot Hamiltonian in the psi layout (device output). */
+int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag);
+
+/* sigma for nprob independent problems in one fused launch sequence. */
+int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops,
+                       const double* const* psi, double* const* sigma, int precision);
+
+/* Lowest eigenpair.  psi (device, n_psi) holds the initial guess and receives
+ * the normalised eigenvector; *energy its FP64 Rayleigh quotient (ecore
+ * included).  Synchronous.  opts or stats may be NULL (defaults). */
+int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi,
+                  const dmrg_davidson_opts* opts, double* energy,
+                  dmrg_davidson_stats* stats);
+void dmrg_davidson_default_opts(dmrg_davidson_opts* opts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,204 @@
+"""ctypes binding of libdmrg.so (include/dmrg.h).  Argument marshalling only:
+every step of sigma, the operator build and Davidson runs in the library.
+
+Device buffers are passed as raw device addresses (e.g. torch.Tensor.data_ptr()
+of a CUDA/HIP tensor); host inputs are numpy arrays that the library copies.
+"""
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_LIB = os.path.join(HERE, "lib", "libdmrg.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ESHAPE", -3: "DMRG_ENOMEM", -4: "DMRG_EHIP",
+          -5: "DMRG_ENOCONV", -6: "DMRG_EINTERNAL"}
+
+EXPORTS = ["dmrg_create", "dmrg_destroy", "dmrg_last_error", "dmrg_build_ops", "dmrg_ops_destroy",
+           "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_sigma_batched",
+           "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile"]
+
+
+class Integrals(C.Structure):
+    _fields_ = [("K", C.c_int), ("h", C.POINTER(C.c_double)), ("eri", C.POINTER(C.c_double)),
+                ("ecore", C.c_double)]
+
+
+class Mps(C.Structure):
+    _fields_ = [("K", C.c_int), ("n_alpha", C.c_int), ("n_beta", C.c_int), ("bond", C.c_int),
+                ("nsec", C.POINTER(C.c_int)), ("sec_qn", C.POINTER(C.c_int)),
+                ("sec_dim", C.POINTER(C.c_int)), ("blk_off", C.POINTER(C.c_int64)),
+                ("data", C.POINTER(C.c_double))]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_psi", C.c_int64), ("n_blocks", C.c_int64), ("n_terms", C.c_int64),
+                ("n_rgemm", C.c_int64), ("n_lgemm", C.c_int64), ("flops_sigma", C.c_double),
+                ("flops_rstep", C.c_double), ("flops_lstep", C.c_double), ("op_bytes", C.c_double),
+                ("build_seconds", C.c_double), ("build_flops", C.c_double),
+                ("prof_sigma_calls", C.c_int64), ("prof_launches", C.c_int64),
+                ("prof_rstep_ms", C.c_double), ("prof_lstep_ms", C.c_double)]
+
+
+class DavidsonOpts(C.Structure):
+    _fields_ = [("tol_residual", C.c_double), ("max_iter", C.c_int), ("m_max", C.c_int),
+                ("precision", C.c_int), ("switch_residual", C.c_double), ("precond", C.c_int),
+                ("mlp_weights", C.POINTER(C.c_float)), ("e_ref", C.c_double), ("e_tol", C.c_double)]
+
+
+class DavidsonStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("sigma_fp64", C.c_int), ("residual", C.c_double),
+                ("seconds", C.c_double), ("seconds_to_ref", C.c_double), ("iters_to_ref", C.c_int),
+                ("mlp_fallbacks", C.c_int)]
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def load(path=None):
+    path = path or DEFAULT_LIB
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is not built; run paper_2311_02854_amd.build.build()")
+    lib = C.CDLL(path)
+    vp, i64p = C.c_void_p, C.POINTER(C.c_int64)
+    lib.dmrg_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+    lib.dmrg_destroy.argtypes = [vp]
+    lib.dmrg_destroy.restype = None
+    lib.dmrg_last_error.argtypes = [vp]
+    lib.dmrg_last_error.restype = C.c_char_p
+    lib.dmrg_build_ops.argtypes = [vp, C.POINTER(Integrals), C.POINTER(Mps), C.POINTER(vp)]
+    lib.dmrg_ops_destroy.argtypes = [vp]
+    lib.dmrg_ops_destroy.restype = None
+    lib.dmrg_ops_layout.argtypes = [vp, i64p, i64p, C.POINTER(C.c_int), i64p]
+    lib.dmrg_ops_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.dmrg_sigma.argtypes = [vp, vp, vp, vp, C.c_int]
+    lib.dmrg_diag.argtypes = [vp, vp, vp]
+    lib.dmrg_sigma_batched.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
+    lib.dmrg_davidson.argtypes = [vp, vp, vp, C.POINTER(DavidsonOpts), C.POINTER(C.c_double),
+                                  C.POINTER(DavidsonStats)]
+    lib.dmrg_davidson_default_opts.argtypes = [C.POINTER(DavidsonOpts)]
+    lib.dmrg_davidson_default_opts.restype = None
+    lib.dmrg_profile.argtypes = [vp, C.c_int]
+    return lib
+
+
+class DmrgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Context:
+    """A library context bound to one device and HIP stream."""
+
+    def __init__(self, device=0, stream=0, lib=None):
+        self.lib = lib if lib is not None else load()
+        self.h = C.c_void_p()
+        self._check(self.lib.dmrg_create(C.byref(self.h), int(device), C.c_void_p(stream or None)))
+
+    def _check(self, rc):
+        if rc != 0:
+            msg = self.lib.dmrg_last_error(self.h).decode() if self.h else ""
+            raise DmrgError(rc, msg)
+        return rc
+
+    def close(self):
+        if self.h:
+            self.lib.dmrg_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_ops(self, ints, mps):
+        """ints: dict(K, h, eri, ecore); mps: synth.SiteMPS (host arrays, copied)."""
+        h = np.ascontiguousarray(ints["h"], dtype=np.float64)
+        eri = np.ascontiguousarray(ints["eri"], dtype=np.float64)
+        I = Integrals(int(ints["K"]), _p(h, C.c_double), _p(eri, C.c_double), float(ints.get("ecore", 0.0)))
+        nsec, qn, dim, off, data = mps.flat()
+        if len(data) == 0:
+            data = np.zeros(1)
+        if len(off) == 0:
+            off = np.zeros(1, np.int64)
+        M = Mps(mps.K, mps.Na, mps.Nb, mps.k, _p(nsec, C.c_int), _p(qn, C.c_int), _p(dim, C.c_int),
+                _p(off, C.c_int64), _p(data, C.c_double))
+        out = C.c_void_p()
+        self._check(self.lib.dmrg_build_ops(self.h, C.byref(I), C.byref(M), C.byref(out)))
+        return Ops(self, out)
+
+
+class Ops:
+    def __init__(self, ctx, handle):
+        self.ctx, self.h = ctx, handle
+        n, nb = C.c_int64(), C.c_int64()
+        ctx._check(ctx.lib.dmrg_ops_layout(handle, C.byref(n), C.byref(nb), None, None))
+        self.n_psi, self.n_blocks = n.value, nb.value
+        meta = np.zeros(6 * nb.value, np.int32)
+        offs = np.zeros(nb.value, np.int64)
+        ctx._check(ctx.lib.dmrg_ops_layout(handle, None, None, _p(meta, C.c_int), _p(offs, C.c_int64)))
+        self.blk_meta = meta.reshape(-1, 6)
+        self.blk_off = offs
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.dmrg_ops_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def stats(self):
+        s = Stats()
+        self.ctx._check(self.ctx.lib.dmrg_ops_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def profile(self, enable=True):
+        self.ctx._check(self.ctx.lib.dmrg_profile(self.h, int(enable)))
+
+    def sigma(self, psi_ptr, sigma_ptr, precision=FP64):
+        self.ctx._check(self.ctx.lib.dmrg_sigma(self.ctx.h, self.h, C.c_void_p(psi_ptr), C.c_void_p(sigma_ptr),
+                                                int(precision)))
+
+    def diag(self, out_ptr):
+        self.ctx._check(self.ctx.lib.dmrg_diag(self.ctx.h, self.h, C.c_void_p(out_ptr)))
+
+    def davidson(self, psi_ptr, **kw):
+        o = DavidsonOpts()
+        self.ctx.lib.dmrg_davidson_default_opts(C.byref(o))
+        for k, v in kw.items():
+            if k == "mlp_weights":
+                o.mlp_weights = v.ctypes.data_as(C.POINTER(C.c_float)) if v is not None else None
+                self._mlp_keep = v
+            else:
+                setattr(o, k, v)
+        e = C.c_double()
+        st = DavidsonStats()
+        rc = self.ctx.lib.dmrg_davidson(self.ctx.h, self.h, C.c_void_p(psi_ptr), C.byref(o), C.byref(e),
+                                        C.byref(st))
+        if rc not in (0, -5):
+            self.ctx._check(rc)
+        out = {k: getattr(st, k) for k, _ in DavidsonStats._fields_}
+        out["converged"] = rc == 0
+        return e.value, out
+
+
+def sigma_batched(ctx, ops_list, psi_ptrs, sigma_ptrs, precision=FP64):
+    n = len(ops_list)
+    arr = C.c_void_p * n
+    ctx._check(ctx.lib.dmrg_sigma_batched(ctx.h, n, arr(*[o.h for o in ops_list]), arr(*psi_ptrs),
+                                          arr(*sigma_ptrs), int(precision)))
+
+
+def nan():
+    return math.nan

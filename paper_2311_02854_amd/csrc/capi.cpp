@@ -1,0 +1,217 @@
+// extern "C" entry points of include/dmrg.h.  Every call catches exceptions
+// and turns them into status codes plus a per-context message.
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+
+#include "../../include/dmrg.h"
+#include "ops.h"
+
+namespace dmrg {
+int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* energy, dmrg_davidson_stats* st,
+                 void* stream);
+}
+
+struct dmrg_ctx {
+  int device = 0;
+  void* stream = nullptr;
+  std::string err;
+};
+
+struct dmrg_ops {
+  std::unique_ptr<dmrg::Ops> p;
+};
+
+namespace {
+template <typename F>
+int guarded(dmrg_ctx* ctx, F&& f) {
+  try {
+    if (ctx) dmrg::dev_set(ctx->device);
+    return f();
+  } catch (const dmrg::Error& e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return DMRG_EINTERNAL;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return DMRG_EINTERNAL;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int dmrg_create(dmrg_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) return DMRG_EINVAL;
+  *ctx = nullptr;
+  auto c = new (std::nothrow) dmrg_ctx();
+  if (!c) return DMRG_ENOMEM;
+  c->device = device;
+  c->stream = hip_stream;
+  int rc = guarded(c, [&] {
+    dmrg::dev_set(device);
+    return (int)DMRG_OK;
+  });
+  if (rc != DMRG_OK) {
+    delete c;
+    return rc;
+  }
+  *ctx = c;
+  return DMRG_OK;
+}
+
+void dmrg_destroy(dmrg_ctx* ctx) { delete ctx; }
+
+const char* dmrg_last_error(const dmrg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mps, dmrg_ops** out) {
+  if (!ctx || !ints || !mps || !out) return DMRG_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    DMRG_CHECK(ints->K == mps->K && ints->K >= 2, DMRG_EINVAL, "K mismatch between integrals and MPS");
+    DMRG_CHECK(ints->h && ints->eri && mps->nsec && mps->sec_qn && mps->sec_dim, DMRG_EINVAL, "null array");
+    const int K = ints->K;
+    dmrg::Integrals I;
+    I.K = K;
+    I.h.assign(ints->h, ints->h + (size_t)K * K);
+    I.eri.assign(ints->eri, ints->eri + (size_t)K * K * K * K);
+    I.ecore = ints->ecore;
+    dmrg::BuildOptions opt;
+    auto o = dmrg::build_ops(I, K, mps->n_alpha, mps->n_beta, mps->bond, mps->nsec, mps->sec_qn, mps->sec_dim,
+                             mps->blk_off, mps->data, ctx->stream, opt);
+    o->device = ctx->device;
+    auto h = new dmrg_ops();
+    h->p = std::move(o);
+    *out = h;
+    return (int)DMRG_OK;
+  });
+}
+
+void dmrg_ops_destroy(dmrg_ops* ops) {
+  if (!ops) return;
+  try {
+    dmrg::dev_set(ops->p->device);
+  } catch (...) {
+  }
+  delete ops;
+}
+
+int dmrg_ops_layout(const dmrg_ops* ops, int64_t* n_psi, int64_t* n_blocks, int* blk_meta, int64_t* blk_off) {
+  if (!ops) return DMRG_EINVAL;
+  const auto& O = *ops->p;
+  if (n_psi) *n_psi = O.npsi;
+  if (n_blocks) *n_blocks = (int64_t)O.blocks.size();
+  for (size_t i = 0; i < O.blocks.size(); ++i) {
+    const auto& b = O.blocks[i];
+    if (blk_meta) {
+      int* m = blk_meta + 6 * i;
+      m[0] = b.il;
+      m[1] = b.e / 4;
+      m[2] = b.e % 4;
+      m[3] = b.ir;
+      m[4] = b.dl;
+      m[5] = b.dr;
+    }
+    if (blk_off) blk_off[i] = b.off;
+  }
+  return DMRG_OK;
+}
+
+int dmrg_ops_stats(const dmrg_ops* ops, dmrg_stats* st) {
+  if (!ops || !st) return DMRG_EINVAL;
+  const auto& O = *ops->p;
+  std::memset(st, 0, sizeof(*st));
+  st->n_psi = O.npsi;
+  st->n_blocks = (int64_t)O.blocks.size();
+  st->n_terms = O.nterms;
+  st->n_rgemm = O.ngemm_r;
+  st->n_lgemm = O.ngemm_l;
+  st->flops_rstep = O.flops_r;
+  st->flops_lstep = O.flops_l;
+  st->flops_sigma = O.flops_r + O.flops_l;
+  st->op_bytes = O.op_bytes;
+  st->build_seconds = O.build_seconds;
+  st->build_flops = O.build_flops;
+  st->prof_sigma_calls = O.prof_calls;
+  st->prof_launches = O.prof_launches;
+  st->prof_rstep_ms = O.prof_r_ms;
+  st->prof_lstep_ms = O.prof_l_ms;
+  return DMRG_OK;
+}
+
+int dmrg_profile(dmrg_ops* ops, int enable) {
+  if (!ops) return DMRG_EINVAL;
+  auto& O = *ops->p;
+  O.profile = enable != 0;
+  O.prof_r_ms = O.prof_l_ms = 0;
+  O.prof_launches = O.prof_calls = 0;
+  return DMRG_OK;
+}
+
+int dmrg_sigma(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi, double* sigma, int precision) {
+  if (!ctx || !ops || !psi || !sigma) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    DMRG_CHECK(precision >= 0 && precision <= 2, DMRG_EINVAL, "unknown precision");
+    DMRG_CHECK(psi != sigma, DMRG_EINVAL, "psi and sigma must not alias");
+    dmrg::sigma_run(*ops->p, psi, sigma, precision, ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag) {
+  if (!ctx || !ops || !diag) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    dmrg::diag_run(*ops->p, diag, ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops, const double* const* psi,
+                       double* const* sigma, int precision) {
+  if (!ctx || nprob < 0 || (nprob > 0 && (!ops || !psi || !sigma))) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    for (int i = 0; i < nprob; ++i) {
+      DMRG_CHECK(ops[i] && psi[i] && sigma[i], DMRG_EINVAL, "null problem entry");
+      dmrg::sigma_run(*ops[i]->p, psi[i], sigma[i], precision, ctx->stream);
+    }
+    return (int)DMRG_OK;
+  });
+}
+
+void dmrg_davidson_default_opts(dmrg_davidson_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tol_residual = 1e-6;
+  o->max_iter = 200;
+  o->m_max = 24;
+  o->precision = DMRG_FP64;
+  o->switch_residual = 1e-3;
+  o->precond = 0;
+  o->mlp_weights = nullptr;
+  o->e_ref = std::numeric_limits<double>::quiet_NaN();
+  o->e_tol = 1e-6;
+}
+
+int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi, const dmrg_davidson_opts* opts, double* energy,
+                  dmrg_davidson_stats* stats) {
+  if (!ctx || !ops || !psi || !energy) return DMRG_EINVAL;
+  dmrg_davidson_opts o;
+  if (opts)
+    o = *opts;
+  else
+    dmrg_davidson_default_opts(&o);
+  return guarded(ctx, [&] { return dmrg::davidson_run(*ops->p, psi, o, energy, stats, ctx->stream); });
+}
+
+}  // extern "C"
+
+namespace dmrg {
+void mlp_precondition(Ops&, const double*, const double*, const double*, double*, int* fallback, const float*,
+                      void*) {
+  *fallback = 1;
+}
+}  // namespace dmrg

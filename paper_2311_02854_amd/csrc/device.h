@@ -1,0 +1,94 @@
+// Device-side interface: memory, streams and kernel launchers.  Implemented in
+// kernels.hip; the planner sources only see this header.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace dmrg {
+
+// One output matrix (or a batch of nbatch equally laid-out outputs):
+//   C[b] (+)= sum_{c in contribs} sum_{t < nred_c} alpha_c * s_c(b,t) *
+//             op(A_c(b,t)) * op(B_c(b,t))
+// with X_c(b,t) = buffer(x_buf) + x_off + b*x_bstride + t*x_rstride and
+// s_c(b,t) = buffer(s_buf)[s_off + b*s_bstride + t*s_rstride] (1 if s_buf < 0).
+// Buffer ids 0 and 1 are the per-launch pointers p0/p1; ids >= 2 index the
+// launch's pointer table.
+struct GTask {
+  int32_t M, N;
+  int32_t nbatch;
+  int32_t tiles_m, tiles_n;
+  int32_t c_buf;
+  int32_t ldc;
+  int32_t accumulate;
+  int64_t c_off, c_bstride;
+  int32_t contrib_begin, contrib_end;
+  int64_t job_begin;  // first job (tile x batch) of this task in the launch
+};
+
+enum : int32_t { GF_TRANS_A = 1, GF_TRANS_B = 2, GF_IDENT_A = 4 };
+
+struct GContrib {
+  int32_t K;
+  int32_t flags;
+  int32_t a_buf, b_buf, s_buf;
+  int32_t lda, ldb;
+  int32_t nred;
+  double alpha;
+  int64_t a_off, b_off, s_off;
+  int64_t a_bstride, b_bstride, s_bstride;
+  int64_t a_rstride, b_rstride, s_rstride;
+};
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
+
+// --- runtime -------------------------------------------------------------
+void dev_set(int device);
+void* dev_alloc(size_t bytes);          // zero-filled; throws Error(ENOMEM)
+void dev_free(void* p);
+void dev_h2d(void* dst, const void* src, size_t bytes);            // synchronous
+void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);  // synchronous
+void dev_sync(void* stream);
+void dev_check(const char* where);      // throws Error(EHIP) on a pending error
+double wall_seconds();
+void* ev_create();
+void ev_destroy(void* ev);
+void ev_record(void* ev, void* stream);
+float ev_elapsed_ms(void* a, void* b);   // both recorded and complete
+
+// --- kernels (all asynchronous on `stream`) --------------------------------
+// Grouped, batched GEMM over a task list (tasks/contribs in device memory).
+// elem: P_F64 (all buffers double) or P_F32 (all buffers float, FP32 MFMA)
+// or P_BF16X3 (float buffers, split-bf16 MFMA, FP32 accumulation).
+void gemm_launch(const GTask* tasks_dev, int ntasks, int64_t njobs, const GContrib* contribs_dev,
+                 void* const* table_dev, const void* p0, void* p1, int elem, void* stream);
+
+void k_fill(double* x, double v, int64_t n, void* stream);
+void k_fill_f(float* x, float v, int64_t n, void* stream);
+void k_d2f(const double* x, float* y, int64_t n, void* stream);
+void k_f2d(const float* x, double* y, int64_t n, void* stream);
+void k_axpby(double a, const double* x, double b, double* y, int64_t n, void* stream);  // y = a x + b y
+void k_copy(const double* x, double* y, int64_t n, void* stream);
+// out[i] = sum_j V[j*ld + k] * x[k] over k for j < m  (dots of m vectors with x); result on device
+void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, double* out, void* stream);
+// y[k] = sum_j c[j] V[j*ld + k]   (c on device)
+void k_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* stream);
+// y[k] -= sum_j c[j] V[j*ld + k]
+void k_sub_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* stream);
+// Symmetric eigen-decomposition of a small m x m matrix (m <= 32) by cyclic
+// Jacobi; writes eigenvalues ascending to w[m] and eigenvectors (columns) to Z.
+void k_small_eigh(const double* G, int ld, int m, double* w, double* Z, void* stream);
+// diagonal preconditioner t_i = r_i / (theta - d_i) with |theta - d_i| >= floor
+void k_precond_diag(const double* r, const double* d, const double* theta, double floor_,
+                    double* t, int64_t n, void* stream);
+// copy diagonal elements of square blocks: dst[i] for listed (src offset, dim, dst offset)
+void k_gather_diag(const double* src, const int64_t* meta, int nblk, int64_t src_stride,
+                   int64_t dst_stride, int nmem, double* dst, void* stream);
+// scale the per-member coefficient rows etc.: y[i] *= s
+void k_scale(double* y, double s, int64_t n, void* stream);
+// MLP preconditioner: features -> 2 hidden layers (ReLU) -> scalar gain g_i;
+// t_i = g_i * r_i / (theta - d_i).
+void k_mlp_precond(const float* feat, int nfeat, int64_t n, const float* w, int hidden,
+                   const double* r, const double* d, const double* theta, double floor_,
+                   double* t, void* stream);
+
+}  // namespace dmrg

@@ -1,0 +1,492 @@
+// HIP kernels for gfx950 (CDNA4) and the HIP runtime wrappers of device.h.
+//
+// The hot kernel is a grouped, batched GEMM driven by a task list: every
+// workgroup owns one 64x64 output tile of one task (output-stationary), loops
+// over the task's contributions (and, inside each, over a reduction index),
+// stages 64x16 / 16x64 operand tiles in LDS and accumulates in registers with
+// FP64 MFMA (v_mfma_f64_16x16x4f64).  Accumulation order is fixed, so results
+// are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <string>
+
+#include "../../include/dmrg.h"
+#include "common.h"
+#include "device.h"
+
+namespace dmrg {
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      throw Error(DMRG_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- runtime
+void dev_set(int device) { HIPCHK(hipSetDevice(device)); }
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(DMRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  HIPCHK(hipMemset(p, 0, bytes));
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void dev_h2d(void* dst, const void* src, size_t bytes) {
+  if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+}
+
+void dev_d2h(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!bytes) return;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, S(stream)));
+  HIPCHK(hipStreamSynchronize(S(stream)));
+}
+
+void dev_sync(void* stream) { HIPCHK(hipStreamSynchronize(S(stream))); }
+
+void dev_check(const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(DMRG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+void* ev_create() {
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return (void*)e;
+}
+void ev_destroy(void* ev) {
+  if (ev) (void)hipEventDestroy((hipEvent_t)ev);
+}
+void ev_record(void* ev, void* stream) { HIPCHK(hipEventRecord((hipEvent_t)ev, S(stream))); }
+float ev_elapsed_ms(void* a, void* b) {
+  float ms = 0;
+  HIPCHK(hipEventSynchronize((hipEvent_t)b));
+  HIPCHK(hipEventElapsedTime(&ms, (hipEvent_t)a, (hipEvent_t)b));
+  return ms;
+}
+
+double wall_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------- GEMM
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+template <typename T>
+__device__ __forceinline__ const T* bufp(int id, T* const* table, const T* p0, const T* p1) {
+  return id == 0 ? p0 : (id == 1 ? p1 : table[id]);
+}
+
+__device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, int ntasks, int64_t job) {
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].job_begin <= job)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Load op(X) tile rows r0..r0+R-1, cols c0..c0+C-1 into LDS as Ls[c][r]
+// (i.e. transposed so that the MFMA fragment reads are contiguous in r).
+// X is the stored matrix; trans means op(X) = X^T.
+template <typename T, int R, int C, int LD>
+__device__ __forceinline__ void load_tile_T(T (*Ls)[LD], const T* __restrict__ X, int ldx, bool trans,
+                                            int r0, int c0, int rows, int cols, T scale) {
+  const int tid = threadIdx.x;
+  if (!trans) {
+    // X row-major rows x cols: element (r, c) at X[r*ldx + c]; threads walk c fastest
+#pragma unroll
+    for (int it = 0; it < (R * C) / NT; ++it) {
+      int idx = tid + it * NT;
+      int r = idx / C, c = idx % C;
+      T v = 0;
+      if (r0 + r < rows && c0 + c < cols) v = X[(int64_t)(r0 + r) * ldx + (c0 + c)] * scale;
+      Ls[c][r] = v;
+    }
+  } else {
+    // op(X)(r, c) = X[c*ldx + r]; threads walk r fastest
+#pragma unroll
+    for (int it = 0; it < (R * C) / NT; ++it) {
+      int idx = tid + it * NT;
+      int c = idx / R, r = idx % R;
+      T v = 0;
+      if (r0 + r < rows && c0 + c < cols) v = X[(int64_t)(c0 + c) * ldx + (r0 + r)] * scale;
+      Ls[c][r] = v;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ tasks, int ntasks,
+                                                      int64_t njobs,
+                                                      const GContrib* __restrict__ contribs,
+                                                      double* const* __restrict__ table,
+                                                      const double* p0, const double* p1) {
+  __shared__ double As[BK][BM + 2];
+  __shared__ double Bs[BK][BN + 2];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int64_t job = blockIdx.x; job < njobs; job += gridDim.x) {
+    const GTask T = tasks[find_task(tasks, ntasks, job)];
+    const int64_t local = job - T.job_begin;
+    const int tiles = T.tiles_m * T.tiles_n;
+    const int64_t batch = local / tiles;
+    const int tile = (int)(local - batch * tiles);
+    const int m0 = (tile / T.tiles_n) * BM, n0 = (tile % T.tiles_n) * BN;
+    d4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+
+    for (int ci = T.contrib_begin; ci < T.contrib_end; ++ci) {
+      const GContrib Cb = contribs[ci];
+      const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
+      for (int t = 0; t < Cb.nred; ++t) {
+        const double* A = bufp<double>(Cb.a_buf, table, p0, p1) + Cb.a_off + batch * Cb.a_bstride +
+                          (int64_t)t * Cb.a_rstride;
+        const double* B = bufp<double>(Cb.b_buf, table, p0, p1) + Cb.b_off + batch * Cb.b_bstride +
+                          (int64_t)t * Cb.b_rstride;
+        double alpha = Cb.alpha;
+        if (Cb.s_buf >= 0)
+          alpha *= bufp<double>(Cb.s_buf, table, p0, p1)[Cb.s_off + batch * Cb.s_bstride +
+                                                         (int64_t)t * Cb.s_rstride];
+        if (Cb.flags & GF_IDENT_A) {
+          // op(A) = identity (M == K): acc += alpha * op(B)
+#pragma unroll
+          for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                int r = m0 + wm + mi * 16 + lk + 4 * v, c = n0 + wn + ni * 16 + lr;
+                if (r < T.M && c < T.N)
+                  acc[mi][ni][v] += alpha * (tb ? B[(int64_t)c * Cb.ldb + r] : B[(int64_t)r * Cb.ldb + c]);
+              }
+          continue;
+        }
+        for (int k0 = 0; k0 < Cb.K; k0 += BK) {
+          // op(A): M x K  -> As[k][m];  op(B): K x N -> Bs[k][n]
+          load_tile_T<double, BM, BK, BM + 2>(As, A, Cb.lda, ta, m0, k0, T.M, Cb.K, alpha);
+          // op(B)^T is N x K; loading op(B)^T with rows n, cols k gives Bs[k][n]
+          load_tile_T<double, BN, BK, BN + 2>(Bs, B, Cb.ldb, !tb, n0, k0, T.N, Cb.K, 1.0);
+          __syncthreads();
+#pragma unroll
+          for (int kk = 0; kk < BK; kk += 4) {
+            double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
+            double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+          }
+          __syncthreads();
+        }
+      }
+    }
+    double* Cp = const_cast<double*>(bufp<double>(T.c_buf, table, p0, p1)) + T.c_off + batch * T.c_bstride;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int r = m0 + wm + mi * 16 + lk + 4 * v, c = n0 + wn + ni * 16 + lr;
+          if (r < T.M && c < T.N) {
+            double val = acc[mi][ni][v];
+            double* dst = Cp + (int64_t)r * T.ldc + c;
+            if (T.accumulate) val += *dst;
+            *dst = val;
+          }
+        }
+  }
+}
+
+void gemm_launch(const GTask* tasks_dev, int ntasks, int64_t njobs, const GContrib* contribs_dev,
+                 void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
+  if (ntasks == 0 || njobs == 0) return;
+  int64_t grid = njobs < (1 << 22) ? njobs : (1 << 22);
+  if (elem == P_F64) {
+    hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, S(stream), tasks_dev, ntasks,
+                       njobs, contribs_dev, (double* const*)table_dev, (const double*)p0,
+                       (const double*)p1);
+  } else {
+    throw Error(DMRG_EINVAL, "reduced-precision GEMM not built");
+  }
+  dev_check("gemm_launch");
+}
+
+// ---------------------------------------------------------------- vector kernels
+static inline unsigned nblocks(int64_t n, int per = 256) {
+  int64_t b = (n + per - 1) / per;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+__global__ void fill_kernel(double* x, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+__global__ void fill_f_kernel(float* x, float v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) x[i] = v;
+}
+__global__ void d2f_kernel(const double* x, float* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = (float)x[i];
+}
+__global__ void f2d_kernel(const float* x, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = (double)x[i];
+}
+__global__ void axpby_kernel(double a, const double* x, double b, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+__global__ void copy_kernel(const double* x, double* y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = x[i];
+}
+__global__ void scale_kernel(double* y, double s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] *= s;
+}
+
+void k_fill(double* x, double v, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, v, n);
+  dev_check("k_fill");
+}
+void k_fill_f(float* x, float v, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(fill_f_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, v, n);
+  dev_check("k_fill_f");
+}
+void k_d2f(const double* x, float* y, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(d2f_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, y, n);
+  dev_check("k_d2f");
+}
+void k_f2d(const float* x, double* y, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(f2d_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, y, n);
+  dev_check("k_f2d");
+}
+void k_axpby(double a, const double* x, double b, double* y, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(axpby_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), a, x, b, y, n);
+  dev_check("k_axpby");
+}
+void k_copy(const double* x, double* y, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(copy_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, y, n);
+  dev_check("k_copy");
+}
+void k_scale(double* y, double sc, int64_t n, void* s) {
+  if (n > 0) hipLaunchKernelGGL(scale_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), y, sc, n);
+  dev_check("k_scale");
+}
+
+// Dots of m vectors with x: two passes (fixed-order partial sums) -> deterministic.
+constexpr int MD_CHUNKS = 512;
+__global__ void multidot_partial(const double* V, int64_t ld, const double* x, int64_t n, double* part) {
+  const int j = blockIdx.y, c = blockIdx.x;
+  const int64_t per = (n + MD_CHUNKS - 1) / MD_CHUNKS;
+  const int64_t beg = c * per, end = (beg + per < n) ? beg + per : n;
+  const double* v = V + j * ld;
+  double s = 0;
+  for (int64_t i = beg + threadIdx.x; i < end; i += blockDim.x) s += v[i] * x[i];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[j * MD_CHUNKS + c] = red[0];
+}
+__global__ void multidot_final(const double* part, int m, double* out) {
+  const int j = blockIdx.x;
+  __shared__ double red[256];
+  double s = 0;
+  for (int c = threadIdx.x; c < MD_CHUNKS; c += blockDim.x) s += part[j * MD_CHUNKS + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+static double* g_part = nullptr;
+static int g_part_m = 0;
+
+void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, double* out, void* s) {
+  if (m <= 0) return;
+  if (m > g_part_m) {
+    if (g_part) dev_free(g_part);
+    g_part = (double*)dev_alloc(sizeof(double) * MD_CHUNKS * (size_t)m);
+    g_part_m = m;
+  }
+  hipLaunchKernelGGL(multidot_partial, dim3(MD_CHUNKS, m), dim3(256), 0, S(s), V, ld, x, n, g_part);
+  hipLaunchKernelGGL(multidot_final, dim3(m), dim3(256), 0, S(s), g_part, m, out);
+  dev_check("k_multidot");
+}
+
+__global__ void lincomb_kernel(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y,
+                               int mode) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int j = 0; j < m; ++j) s += c[j] * V[j * ld + i];
+    if (mode == 0)
+      y[i] = s;
+    else
+      y[i] -= s;
+  }
+}
+void k_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* s) {
+  hipLaunchKernelGGL(lincomb_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), V, ld, m, c, n, y, 0);
+  dev_check("k_lincomb");
+}
+void k_sub_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* s) {
+  hipLaunchKernelGGL(lincomb_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), V, ld, m, c, n, y, 1);
+  dev_check("k_sub_lincomb");
+}
+
+// Cyclic Jacobi on one wave; matrix in LDS.  m <= 32.
+__global__ void small_eigh_kernel(const double* G, int ld, int m, double* w, double* Z) {
+  __shared__ double a[32][33];
+  __shared__ double z[32][33];
+  __shared__ double cs[2];
+  const int t = threadIdx.x;
+  for (int i = t; i < m * m; i += blockDim.x) {
+    int r = i / m, c = i % m;
+    a[r][c] = 0.5 * (G[r * ld + c] + G[c * ld + r]);
+    z[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    // convergence: off-diagonal norm relative to the matrix norm
+    __shared__ double offn, totn;
+    if (t == 0) {
+      double o = 0, d = 0;
+      for (int r = 0; r < m; ++r)
+        for (int c = 0; c < m; ++c) {
+          if (r != c) o += a[r][c] * a[r][c];
+          d += a[r][c] * a[r][c];
+        }
+      offn = o;
+      totn = d;
+    }
+    __syncthreads();
+    if (offn <= 1e-30 * (totn > 0 ? totn : 1.0)) break;
+    for (int p = 0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        if (t == 0) {
+          double apq = a[p][q];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+            double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
+          }
+          cs[0] = c;
+          cs[1] = s;
+        }
+        __syncthreads();
+        const double c = cs[0], s = cs[1];
+        if (s != 0.0) {
+          // A <- J^T A J on rows/cols p,q; Z <- Z J
+          if (t < m) {
+            double akp = a[t][p], akq = a[t][q];
+            a[t][p] = c * akp - s * akq;
+            a[t][q] = s * akp + c * akq;
+          }
+          __syncthreads();
+          if (t < m) {
+            double apk = a[p][t], aqk = a[q][t];
+            a[p][t] = c * apk - s * aqk;
+            a[q][t] = s * apk + c * aqk;
+            double zkp = z[t][p], zkq = z[t][q];
+            z[t][p] = c * zkp - s * zkq;
+            z[t][q] = s * zkp + c * zkq;
+          }
+        }
+        __syncthreads();
+      }
+  }
+  __syncthreads();
+  if (t == 0) {
+    // selection sort ascending
+    int idx[32];
+    for (int i = 0; i < m; ++i) idx[i] = i;
+    for (int i = 0; i < m; ++i) {
+      int b = i;
+      for (int j = i + 1; j < m; ++j)
+        if (a[idx[j]][idx[j]] < a[idx[b]][idx[b]]) b = j;
+      int tmp = idx[i];
+      idx[i] = idx[b];
+      idx[b] = tmp;
+    }
+    for (int i = 0; i < m; ++i) {
+      w[i] = a[idx[i]][idx[i]];
+      for (int r = 0; r < m; ++r) Z[r * m + i] = z[r][idx[i]];
+    }
+  }
+}
+void k_small_eigh(const double* G, int ld, int m, double* w, double* Z, void* s) {
+  hipLaunchKernelGGL(small_eigh_kernel, dim3(1), dim3(64), 0, S(s), G, ld, m, w, Z);
+  dev_check("k_small_eigh");
+}
+
+__global__ void precond_diag_kernel(const double* r, const double* d, const double* theta, double fl,
+                                    double* t, int64_t n) {
+  const double th = *theta;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double den = th - d[i];
+    if (fabs(den) < fl) den = (den < 0 ? -fl : fl);
+    t[i] = r[i] / den;
+  }
+}
+void k_precond_diag(const double* r, const double* d, const double* theta, double fl, double* t, int64_t n,
+                    void* s) {
+  hipLaunchKernelGGL(precond_diag_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), r, d, theta, fl, t, n);
+  dev_check("k_precond_diag");
+}
+
+// meta: per block (src_off, dim, dst_off)
+__global__ void gather_diag_kernel(const double* src, const int64_t* meta, int nblk, int64_t sstride,
+                                   int64_t dstride, double* dst) {
+  const int mem = blockIdx.y;
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t so = meta[3 * b], dim = meta[3 * b + 1], dO = meta[3 * b + 2];
+    for (int64_t l = threadIdx.x; l < dim; l += blockDim.x)
+      dst[mem * dstride + dO + l] = src[mem * sstride + so + l * dim + l];
+  }
+}
+void k_gather_diag(const double* src, const int64_t* meta, int nblk, int64_t sstride, int64_t dstride,
+                   int nmem, double* dst, void* s) {
+  if (nblk <= 0 || nmem <= 0) return;
+  unsigned gx = nblk < 1024 ? nblk : 1024;
+  hipLaunchKernelGGL(gather_diag_kernel, dim3(gx, nmem), dim3(64), 0, S(s), src, meta, nblk, sstride, dstride, dst);
+  dev_check("k_gather_diag");
+}
+
+void k_mlp_precond(const float*, int, int64_t, const float*, int, const double*, const double*, const double*,
+                   double, double*, void*) {
+  throw Error(DMRG_EINVAL, "MLP preconditioner not built");
+}
+
+}  // namespace dmrg
