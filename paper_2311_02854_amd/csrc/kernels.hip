@@ -160,6 +160,10 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
 
+    // 16x16 sub-tiles of this wave that intersect the output (wave-uniform)
+    const int mrem = T.M - m0 - wm, nrem = T.N - n0 - wn;
+    const bool act00 = mrem > 0 && nrem > 0, act01 = mrem > 0 && nrem > 16;
+    const bool act10 = mrem > 16 && nrem > 0, act11 = mrem > 16 && nrem > 16;
     for (int ci = T.contrib_begin; ci < T.contrib_end; ++ci) {
       const GContrib Cb = contribs[ci];
       const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
@@ -192,14 +196,16 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
           // op(B)^T is N x K; loading op(B)^T with rows n, cols k gives Bs[k][n]
           load_tile_T<double, BN, BK, BN + 2>(Bs, B, Cb.ldb, !tb, n0, k0, T.N, Cb.K, 1.0);
           __syncthreads();
-#pragma unroll
-          for (int kk = 0; kk < BK; kk += 4) {
-            double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
-            double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+          if (act00) {
+            const int kend = (Cb.K - k0 < BK) ? Cb.K - k0 : BK;  // zero-padded k-steps are skipped
+            for (int kk = 0; kk < kend; kk += 4) {
+              double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
+              double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
+              acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+              if (act01) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+              if (act10) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+              if (act11) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
           }
           __syncthreads();
         }
