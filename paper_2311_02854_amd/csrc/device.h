@@ -59,8 +59,11 @@ float ev_elapsed_ms(void* a, void* b);   // both recorded and complete
 // Grouped, batched GEMM over a task list (tasks/contribs in device memory).
 // elem: P_F64 (all buffers double) or P_F32 (all buffers float, FP32 MFMA)
 // or P_BF16X3 (float buffers, split-bf16 MFMA, FP32 accumulation).
+// bucket_dev[b] (b <= njobs >> shift) is the task holding job b << shift
+// (clamped to the last task); it bounds the kernel's job -> task search.
 void gemm_launch(const GTask* tasks_dev, int ntasks, int64_t njobs, const GContrib* contribs_dev,
-                 void* const* table_dev, const void* p0, void* p1, int elem, void* stream);
+                 const int* bucket_dev, int shift, void* const* table_dev, const void* p0, void* p1, int elem,
+                 void* stream);
 
 void k_fill(double* x, double v, int64_t n, void* stream);
 void k_fill_f(float* x, float v, int64_t n, void* stream);

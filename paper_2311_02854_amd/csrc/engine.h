@@ -72,9 +72,12 @@ class GemmList {
       ngemm = o.ngemm;
       dtasks_ = o.dtasks_;
       dcontribs_ = o.dcontribs_;
+      dbucket_ = o.dbucket_;
+      shift_ = o.shift_;
       ntasks_dev_ = o.ntasks_dev_;
       o.dtasks_ = nullptr;
       o.dcontribs_ = nullptr;
+      o.dbucket_ = nullptr;
     }
     return *this;
   }
@@ -124,17 +127,32 @@ class GemmList {
     dev_h2d(dtasks_, tasks.data(), tasks.size() * sizeof(GTask));
     dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
     if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
+    // bucket table: at most 2^16 buckets of 2^shift jobs
+    shift_ = 0;
+    while ((njobs >> shift_) > (int64_t(1) << 16)) ++shift_;
+    const int64_t nb = (njobs >> shift_) + 1;
+    std::vector<int> bucket((size_t)nb + 1);
+    size_t ti = 0;
+    for (int64_t b = 0; b <= nb; ++b) {
+      const int64_t job = b << shift_;
+      while (ti + 1 < tasks.size() && tasks[ti + 1].job_begin <= job) ++ti;
+      bucket[(size_t)b] = (int)ti;
+    }
+    dbucket_ = (int*)dev_alloc(bucket.size() * sizeof(int));
+    dev_h2d(dbucket_, bucket.data(), bucket.size() * sizeof(int));
   }
   void run(DevTable& tab, const void* p0, void* p1, int elem, void* stream) {
     if (!dtasks_) upload();
     if (ntasks_dev_ == 0) return;
-    gemm_launch(dtasks_, ntasks_dev_, njobs, dcontribs_, tab.device(), p0, p1, elem, stream);
+    gemm_launch(dtasks_, ntasks_dev_, njobs, dcontribs_, dbucket_, shift_, tab.device(), p0, p1, elem, stream);
   }
   void release() {
     dev_free(dtasks_);
     dev_free(dcontribs_);
+    dev_free(dbucket_);
     dtasks_ = nullptr;
     dcontribs_ = nullptr;
+    dbucket_ = nullptr;
   }
   void clear_host() {
     std::vector<GTask>().swap(tasks);
@@ -144,6 +162,8 @@ class GemmList {
  private:
   GTask* dtasks_ = nullptr;
   GContrib* dcontribs_ = nullptr;
+  int* dbucket_ = nullptr;
+  int shift_ = 0;
   int ntasks_dev_ = 0;
 };
 

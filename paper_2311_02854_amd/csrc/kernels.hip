@@ -86,17 +86,20 @@ double wall_seconds() {
 
 // ---------------------------------------------------------------- GEMM
 typedef double d4_t __attribute__((ext_vector_type(4)));
-typedef float f4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int BM = 64, BN = 64, BK = 32, NT = 256, LDP = 2;
 
 template <typename T>
 __device__ __forceinline__ const T* bufp(int id, T* const* table, const T* p0, const T* p1) {
   return id == 0 ? p0 : (id == 1 ? p1 : table[id]);
 }
 
-__device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, int ntasks, int64_t job) {
-  int lo = 0, hi = ntasks - 1;
+// Task of a job: the bucket table narrows the search to the tasks that
+// intersect the job's bucket of 2^shift consecutive jobs.
+__device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const int* __restrict__ bucket,
+                                         int shift, int64_t job) {
+  const int64_t b = job >> shift;
+  int lo = bucket[b], hi = bucket[b + 1];
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (tasks[mid].job_begin <= job)
@@ -107,108 +110,179 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, int nt
   return lo;
 }
 
-// Load op(X) tile rows r0..r0+R-1, cols c0..c0+C-1 into LDS as Ls[c][r]
-// (i.e. transposed so that the MFMA fragment reads are contiguous in r).
-// X is the stored matrix; trans means op(X) = X^T.
-template <typename T, int R, int C, int LD>
-__device__ __forceinline__ void load_tile_T(T (*Ls)[LD], const T* __restrict__ X, int ldx, bool trans,
-                                            int r0, int c0, int rows, int cols, T scale) {
+// Per-thread view of one 64 x BK operand tile: element (r, k) of op(X) sits
+// at X + r*sr + k*sk.  When k is contiguous (sk == 1) threads walk k fastest
+// (32 per row, 8 rows per pass), otherwise r fastest (64 per row, 4 k per
+// pass); either way every thread owns 8 elements.
+struct Opnd {
+  const double* base;  // element (r_first, k_first) at k0 = 0
+  int64_t step_it;     // distance between a thread's consecutive elements
+  int64_t step_k;      // distance of one BK tile
+  int r_first, k_first;
+  int r_inc, k_inc;    // increments per element (one of them is 0)
+  int rows, K;         // valid extent (rows counted from the tile origin)
+  double scale;
+};
+
+__device__ __forceinline__ void opnd_setup(Opnd& o, const double* X, int64_t sr, int64_t sk, int r0, int rows,
+                                           int K, double scale) {
   const int tid = threadIdx.x;
-  if (!trans) {
-    // X row-major rows x cols: element (r, c) at X[r*ldx + c]; threads walk c fastest
-#pragma unroll
-    for (int it = 0; it < (R * C) / NT; ++it) {
-      int idx = tid + it * NT;
-      int r = idx / C, c = idx % C;
-      T v = 0;
-      if (r0 + r < rows && c0 + c < cols) v = X[(int64_t)(r0 + r) * ldx + (c0 + c)] * scale;
-      Ls[c][r] = v;
-    }
+  if (sk == 1) {
+    o.r_first = tid >> 5;
+    o.k_first = tid & 31;
+    o.r_inc = 8;
+    o.k_inc = 0;
+    o.step_it = 8 * sr;
   } else {
-    // op(X)(r, c) = X[c*ldx + r]; threads walk r fastest
+    o.r_first = tid & 63;
+    o.k_first = tid >> 6;
+    o.r_inc = 0;
+    o.k_inc = 4;
+    o.step_it = 4 * sk;
+  }
+  o.base = X + (int64_t)(r0 + o.r_first) * sr + (int64_t)o.k_first * sk;
+  o.step_k = (int64_t)BK * sk;
+  o.rows = rows - r0;
+  o.K = K;
+  o.scale = scale;
+}
+
+__device__ __forceinline__ void opnd_load(const Opnd& o, int k0, double (&v)[8]) {
+  const double* p = o.base + (int64_t)(k0 / BK) * o.step_k;
 #pragma unroll
-    for (int it = 0; it < (R * C) / NT; ++it) {
-      int idx = tid + it * NT;
-      int c = idx / R, r = idx % R;
-      T v = 0;
-      if (r0 + r < rows && c0 + c < cols) v = X[(int64_t)(c0 + c) * ldx + (r0 + r)] * scale;
-      Ls[c][r] = v;
-    }
+  for (int it = 0; it < 8; ++it) {
+    const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
+    v[it] = (r < o.rows && k < o.K) ? p[it * o.step_it] * o.scale : 0.0;
   }
 }
 
-__global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ tasks, int ntasks,
-                                                      int64_t njobs,
+__device__ __forceinline__ void opnd_store(const Opnd& o, const double (&v)[8], double (*L)[BM + LDP]) {
+#pragma unroll
+  for (int it = 0; it < 8; ++it) L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = v[it];
+}
+
+// One step of the flattened (contribution, reduction index, k tile) sequence.
+struct Step {
+  int ci, t, k0;
+  int K;
+};
+
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ tasks, int64_t njobs,
                                                       const GContrib* __restrict__ contribs,
-                                                      double* const* __restrict__ table,
-                                                      const double* p0, const double* p1) {
-  __shared__ double As[BK][BM + 2];
-  __shared__ double Bs[BK][BN + 2];
+                                                      const int* __restrict__ bucket, int shift,
+                                                      double* const* __restrict__ table, const double* p0,
+                                                      const double* p1) {
+  __shared__ double As[BK][BM + LDP];
+  __shared__ double Bs[BK][BN + LDP];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
   for (int64_t job = blockIdx.x; job < njobs; job += gridDim.x) {
-    const GTask T = tasks[find_task(tasks, ntasks, job)];
+    const GTask T = tasks[find_task(tasks, bucket, shift, job)];
     const int64_t local = job - T.job_begin;
     const int tiles = T.tiles_m * T.tiles_n;
     const int64_t batch = local / tiles;
     const int tile = (int)(local - batch * tiles);
     const int m0 = (tile / T.tiles_n) * BM, n0 = (tile % T.tiles_n) * BN;
+    const int mrem = T.M - m0 - wm, nrem = T.N - n0 - wn;
+    const bool act00 = mrem > 0 && nrem > 0, act01 = mrem > 0 && nrem > 16;
+    const bool act10 = mrem > 16 && nrem > 0, act11 = mrem > 16 && nrem > 16;
     d4_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
 
-    // 16x16 sub-tiles of this wave that intersect the output (wave-uniform)
-    const int mrem = T.M - m0 - wm, nrem = T.N - n0 - wn;
-    const bool act00 = mrem > 0 && nrem > 0, act01 = mrem > 0 && nrem > 16;
-    const bool act10 = mrem > 16 && nrem > 0, act11 = mrem > 16 && nrem > 16;
+    // identity contributions: acc += alpha op(B)  (M == K)
     for (int ci = T.contrib_begin; ci < T.contrib_end; ++ci) {
-      const GContrib Cb = contribs[ci];
-      const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
+      const GContrib& Cb = contribs[ci];
+      if (!(Cb.flags & GF_IDENT_A)) continue;
+      const bool tb = Cb.flags & GF_TRANS_B;
       for (int t = 0; t < Cb.nred; ++t) {
-        const double* A = bufp<double>(Cb.a_buf, table, p0, p1) + Cb.a_off + batch * Cb.a_bstride +
-                          (int64_t)t * Cb.a_rstride;
         const double* B = bufp<double>(Cb.b_buf, table, p0, p1) + Cb.b_off + batch * Cb.b_bstride +
                           (int64_t)t * Cb.b_rstride;
         double alpha = Cb.alpha;
         if (Cb.s_buf >= 0)
-          alpha *= bufp<double>(Cb.s_buf, table, p0, p1)[Cb.s_off + batch * Cb.s_bstride +
-                                                         (int64_t)t * Cb.s_rstride];
-        if (Cb.flags & GF_IDENT_A) {
-          // op(A) = identity (M == K): acc += alpha * op(B)
+          alpha *= bufp<double>(Cb.s_buf, table, p0, p1)[Cb.s_off + batch * Cb.s_bstride + (int64_t)t * Cb.s_rstride];
 #pragma unroll
-          for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
+          for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                int r = m0 + wm + mi * 16 + lk + 4 * v, c = n0 + wn + ni * 16 + lr;
-                if (r < T.M && c < T.N)
-                  acc[mi][ni][v] += alpha * (tb ? B[(int64_t)c * Cb.ldb + r] : B[(int64_t)r * Cb.ldb + c]);
-              }
-          continue;
-        }
-        for (int k0 = 0; k0 < Cb.K; k0 += BK) {
-          // op(A): M x K  -> As[k][m];  op(B): K x N -> Bs[k][n]
-          load_tile_T<double, BM, BK, BM + 2>(As, A, Cb.lda, ta, m0, k0, T.M, Cb.K, alpha);
-          // op(B)^T is N x K; loading op(B)^T with rows n, cols k gives Bs[k][n]
-          load_tile_T<double, BN, BK, BN + 2>(Bs, B, Cb.ldb, !tb, n0, k0, T.N, Cb.K, 1.0);
-          __syncthreads();
-          if (act00) {
-            const int kend = (Cb.K - k0 < BK) ? Cb.K - k0 : BK;  // zero-padded k-steps are skipped
-            for (int kk = 0; kk < kend; kk += 4) {
-              double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
-              double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
-              acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-              if (act01) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-              if (act10) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-              if (act11) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            for (int v = 0; v < 4; ++v) {
+              int r = m0 + wm + mi * 16 + lk + 4 * v, c = n0 + wn + ni * 16 + lr;
+              if (r < T.M && c < T.N)
+                acc[mi][ni][v] += alpha * (tb ? B[(int64_t)c * Cb.ldb + r] : B[(int64_t)r * Cb.ldb + c]);
             }
+      }
+    }
+
+    // MFMA contributions, software pipelined: the next tile is fetched into
+    // registers while the current one is multiplied out of LDS.
+    auto first_from = [&](int ci) {
+      while (ci < T.contrib_end && (contribs[ci].flags & GF_IDENT_A)) ++ci;
+      return ci;
+    };
+    auto setup = [&](const Step& s, Opnd& oa, Opnd& ob) {
+      const GContrib& Cb = contribs[s.ci];
+      const double* A = bufp<double>(Cb.a_buf, table, p0, p1) + Cb.a_off + batch * Cb.a_bstride +
+                        (int64_t)s.t * Cb.a_rstride;
+      const double* B = bufp<double>(Cb.b_buf, table, p0, p1) + Cb.b_off + batch * Cb.b_bstride +
+                        (int64_t)s.t * Cb.b_rstride;
+      double alpha = Cb.alpha;
+      if (Cb.s_buf >= 0)
+        alpha *= bufp<double>(Cb.s_buf, table, p0, p1)[Cb.s_off + batch * Cb.s_bstride + (int64_t)s.t * Cb.s_rstride];
+      const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
+      // op(A)(m, k): stored M x K (lda) or K x M;  op(B)(k, n) seen as (n, k)
+      opnd_setup(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, T.M, Cb.K, alpha);
+      opnd_setup(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, T.N, Cb.K, 1.0);
+    };
+    Step cur{first_from(T.contrib_begin), 0, 0, 0};
+    if (cur.ci < T.contrib_end) {
+      Opnd oa, ob;
+      cur.K = contribs[cur.ci].K;
+      setup(cur, oa, ob);
+      double ra[8], rb[8];
+      opnd_load(oa, 0, ra);
+      opnd_load(ob, 0, rb);
+      for (;;) {
+        opnd_store(oa, ra, As);
+        opnd_store(ob, rb, Bs);
+        __syncthreads();
+        const int kend = (cur.K - cur.k0 < BK) ? cur.K - cur.k0 : BK;
+        // advance and prefetch
+        Step nxt = cur;
+        nxt.k0 += BK;
+        bool more = true;
+        if (nxt.k0 >= nxt.K) {
+          nxt.k0 = 0;
+          if (++nxt.t >= contribs[nxt.ci].nred) {
+            nxt.t = 0;
+            nxt.ci = first_from(nxt.ci + 1);
+            more = nxt.ci < T.contrib_end;
           }
-          __syncthreads();
+          if (more) {
+            nxt.K = contribs[nxt.ci].K;
+            setup(nxt, oa, ob);
+          }
         }
+        if (more) {
+          opnd_load(oa, nxt.k0, ra);
+          opnd_load(ob, nxt.k0, rb);
+        }
+        if (act00) {
+          for (int kk = 0; kk < kend; kk += 4) {
+            double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
+            double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            if (act01) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            if (act10) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            if (act11) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+          }
+        }
+        __syncthreads();
+        if (!more) break;
+        cur = nxt;
       }
     }
     double* Cp = const_cast<double*>(bufp<double>(T.c_buf, table, p0, p1)) + T.c_off + batch * T.c_bstride;
@@ -230,12 +304,13 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
 }
 
 void gemm_launch(const GTask* tasks_dev, int ntasks, int64_t njobs, const GContrib* contribs_dev,
-                 void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
+                 const int* bucket_dev, int shift, void* const* table_dev, const void* p0, void* p1, int elem,
+                 void* stream) {
   if (ntasks == 0 || njobs == 0) return;
   int64_t grid = njobs < (1 << 22) ? njobs : (1 << 22);
   if (elem == P_F64) {
-    hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, S(stream), tasks_dev, ntasks,
-                       njobs, contribs_dev, (double* const*)table_dev, (const double*)p0,
+    hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, S(stream), tasks_dev, njobs,
+                       contribs_dev, bucket_dev, shift, (double* const*)table_dev, (const double*)p0,
                        (const double*)p1);
   } else {
     throw Error(DMRG_EINVAL, "reduced-precision GEMM not built");
