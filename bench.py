@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="5", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU operator-parallel "
@@ -100,6 +102,14 @@ def main():
         f"sigma plan {st['flops_sigma'] / 1e12:.3f} TFLOP/call, ops {st['op_bytes'] / 1e9:.1f} GB")
     x = torch.from_numpy(psi).cuda()
     y = torch.empty_like(x)
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("[bench] copy probe: 3 x 1 GiB device-to-device copies done")
     for i in range(args.warmup):
         ops.sigma(x.data_ptr(), y.data_ptr())
         torch.cuda.synchronize()
@@ -116,7 +126,7 @@ def main():
     ms = dt / args.steps * 1e3
     flops = st["flops_sigma"]
     tflops = flops / (dt / args.steps) / 1e12
-    kern_ms = (prof["prof_rstep_ms"] + prof["prof_lstep_ms"]) / max(1, prof["prof_sigma_calls"])
+    kern_ms = prof["prof_gemm_ms"] / max(1, prof["prof_sigma_calls"])
     achieved = flops / (kern_ms * 1e-3) / 1e12 if kern_ms > 0 else None
     log(f"[bench] {args.steps} steps: {ms:.1f} ms/call, {tflops:.2f} TFLOP/s; GEMM kernels {kern_ms:.1f} ms/call")
     out = {

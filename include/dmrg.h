@@ -98,8 +98,7 @@ typedef struct {
    * on the context stream around every GEMM launch of dmrg_sigma (FP64) */
   int64_t prof_sigma_calls;
   int64_t prof_launches;
-  double prof_rstep_ms;   /* summed duration of the right-operator launches */
-  double prof_lstep_ms;   /* summed duration of the left-operator launches */
+  double prof_gemm_ms;    /* summed duration of those launches */
 } dmrg_stats;
 
 /* Davidson options (paper Sec. 2.1 names Davidson's method; details are ours). */

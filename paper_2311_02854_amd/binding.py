@@ -41,7 +41,7 @@ class Stats(C.Structure):
                 ("flops_rstep", C.c_double), ("flops_lstep", C.c_double), ("op_bytes", C.c_double),
                 ("build_seconds", C.c_double), ("build_flops", C.c_double),
                 ("prof_sigma_calls", C.c_int64), ("prof_launches", C.c_int64),
-                ("prof_rstep_ms", C.c_double), ("prof_lstep_ms", C.c_double)]
+                ("prof_gemm_ms", C.c_double)]
 
 
 class DavidsonOpts(C.Structure):

@@ -138,8 +138,7 @@ int dmrg_ops_stats(const dmrg_ops* ops, dmrg_stats* st) {
   st->build_flops = O.build_flops;
   st->prof_sigma_calls = O.prof_calls;
   st->prof_launches = O.prof_launches;
-  st->prof_rstep_ms = O.prof_r_ms;
-  st->prof_lstep_ms = O.prof_l_ms;
+  st->prof_gemm_ms = O.prof_ms;
   return DMRG_OK;
 }
 
@@ -147,7 +146,7 @@ int dmrg_profile(dmrg_ops* ops, int enable) {
   if (!ops) return DMRG_EINVAL;
   auto& O = *ops->p;
   O.profile = enable != 0;
-  O.prof_r_ms = O.prof_l_ms = 0;
+  O.prof_ms = 0;
   O.prof_launches = O.prof_calls = 0;
   return DMRG_OK;
 }

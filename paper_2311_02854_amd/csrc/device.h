@@ -22,7 +22,21 @@ struct GTask {
   int32_t accumulate;
   int64_t c_off, c_bstride;
   int32_t contrib_begin, contrib_end;
-  int64_t job_begin;  // first job (tile x batch) of this task in the launch
+  int64_t job_begin;  // first job of this piece in its XCD's job numbering
+  int64_t job_off;    // first job (tile x batch, batch-major) of the piece within the task
+  int64_t njob;       // jobs of the piece
+};
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup i runs on
+// XCD i % NXCD); each XCD walks its own task list so that the tiles sharing
+// operands meet in one L2.
+constexpr int NXCD = 8;
+struct XcdMap {
+  int32_t task_begin[NXCD + 1];    // task range of each XCD in the device task array
+  int32_t bucket_begin[NXCD + 1];  // bucket-table range of each XCD
+  int64_t njobs[NXCD];
+  int64_t max_jobs;
+  int32_t shift;                   // jobs per bucket = 2^shift
 };
 
 enum : int32_t { GF_TRANS_A = 1, GF_TRANS_B = 2, GF_IDENT_A = 4 };
@@ -59,11 +73,10 @@ float ev_elapsed_ms(void* a, void* b);   // both recorded and complete
 // Grouped, batched GEMM over a task list (tasks/contribs in device memory).
 // elem: P_F64 (all buffers double) or P_F32 (all buffers float, FP32 MFMA)
 // or P_BF16X3 (float buffers, split-bf16 MFMA, FP32 accumulation).
-// bucket_dev[b] (b <= njobs >> shift) is the task holding job b << shift
-// (clamped to the last task); it bounds the kernel's job -> task search.
-void gemm_launch(const GTask* tasks_dev, int ntasks, int64_t njobs, const GContrib* contribs_dev,
-                 const int* bucket_dev, int shift, void* const* table_dev, const void* p0, void* p1, int elem,
-                 void* stream);
+// bucket_dev[bucket_begin[x] + b] is the task of XCD x holding its job b << shift
+// (clamped to the XCD's last task); it bounds the kernel's job -> task search.
+void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
+                 const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, void* stream);
 
 void k_fill(double* x, double v, int64_t n, void* stream);
 void k_fill_f(float* x, float v, int64_t n, void* stream);

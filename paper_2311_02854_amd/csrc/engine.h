@@ -1,6 +1,9 @@
 // Host-side helpers around the grouped GEMM kernel: a device pointer table
 // and a task-list builder.
 #pragma once
+#include <algorithm>
+#include <cmath>
+#include <cstring>
 #include <memory>
 #include <vector>
 
@@ -73,7 +76,7 @@ class GemmList {
       dtasks_ = o.dtasks_;
       dcontribs_ = o.dcontribs_;
       dbucket_ = o.dbucket_;
-      shift_ = o.shift_;
+      map_ = o.map_;
       ntasks_dev_ = o.ntasks_dev_;
       o.dtasks_ = nullptr;
       o.dcontribs_ = nullptr;
@@ -119,32 +122,137 @@ class GemmList {
     njobs += (int64_t)t.tiles_m * t.tiles_n * t.nbatch;
   }
   bool empty() const { return tasks.empty() && ntasks_dev_ == 0; }
+
+  // Estimated MFMA work of one job of task t (k steps x active 16x16 sub-tiles).
+  double job_cost(const GTask& t) const {
+    const int am = t.M < TILE ? t.M : TILE, an = t.N < TILE ? t.N : TILE;
+    const double sub = double((am + 15) / 16) * ((an + 15) / 16);
+    double c = 64.0;
+    for (int i = t.contrib_begin; i < t.contrib_end; ++i) {
+      const GContrib& g = contribs[i];
+      c += (g.flags & GF_IDENT_A) ? 4.0 : g.nred * (((g.K + 3) / 4) * sub + 16.0);
+    }
+    return c;
+  }
+
+  // Concatenate host-side lists, ordering tasks by decreasing job cost so the
+  // longest jobs are dispatched first.  Contribution order inside a task is
+  // kept, so results do not depend on the ordering.
+  static GemmList merge_by_cost(const std::vector<GemmList*>& parts) {
+    struct Ref {
+      const GemmList* l;
+      int t;
+      double cost;
+    };
+    std::vector<Ref> refs;
+    GemmList m;
+    for (const GemmList* p : parts) {
+      for (int t = 0; t < (int)p->tasks.size(); ++t) refs.push_back({p, t, p->job_cost(p->tasks[t])});
+      m.flops += p->flops;
+      m.ngemm += p->ngemm;
+    }
+    std::stable_sort(refs.begin(), refs.end(), [](const Ref& a, const Ref& b) { return a.cost > b.cost; });
+    for (const Ref& r : refs) {
+      GTask t = r.l->tasks[r.t];
+      const int cb = (int)m.contribs.size();
+      m.contribs.insert(m.contribs.end(), r.l->contribs.begin() + t.contrib_begin,
+                        r.l->contribs.begin() + t.contrib_end);
+      t.contrib_begin = cb;
+      t.contrib_end = (int)m.contribs.size();
+      t.job_begin = m.njobs;
+      m.njobs += (int64_t)t.tiles_m * t.tiles_n * t.nbatch;
+      m.tasks.push_back(t);
+    }
+    return m;
+  }
+  // Split tasks into job-range pieces, assign them to XCDs (longest
+  // processing time first) and upload the per-XCD task lists.
   void upload() {
     release();
-    ntasks_dev_ = (int)tasks.size();
-    if (tasks.empty()) return;
-    dtasks_ = (GTask*)dev_alloc(tasks.size() * sizeof(GTask));
-    dev_h2d(dtasks_, tasks.data(), tasks.size() * sizeof(GTask));
+    std::vector<GTask> dev;
+    std::memset(&map_, 0, sizeof(map_));
+    if (!tasks.empty()) {
+      std::vector<double> cj(tasks.size());
+      double total = 0;
+      for (size_t t = 0; t < tasks.size(); ++t) {
+        cj[t] = job_cost(tasks[t]);
+        total += cj[t] * jobs_of(tasks[t]);
+      }
+      const double piece_cost = std::max(total / (NXCD * 32.0), 1.0);
+      struct Piece {
+        size_t t;
+        int64_t off, n;
+        double c;
+      };
+      std::vector<Piece> pcs;
+      for (size_t t = 0; t < tasks.size(); ++t) {
+        const int64_t nj = jobs_of(tasks[t]);
+        int64_t np = (int64_t)std::ceil(cj[t] * nj / piece_cost);
+        np = std::max<int64_t>(1, std::min<int64_t>(np, nj));
+        for (int64_t i = 0; i < np; ++i) {
+          const int64_t a = nj * i / np, b = nj * (i + 1) / np;
+          if (b > a) pcs.push_back({t, a, b - a, cj[t]});
+        }
+      }
+      std::stable_sort(pcs.begin(), pcs.end(), [](const Piece& a, const Piece& b) {
+        return a.c * a.n > b.c * b.n;
+      });
+      std::vector<std::vector<Piece>> per(NXCD);
+      double load[NXCD] = {0};
+      for (const Piece& p : pcs) {
+        int x = 0;
+        for (int i = 1; i < NXCD; ++i)
+          if (load[i] < load[x]) x = i;
+        load[x] += p.c * p.n;
+        per[x].push_back(p);
+      }
+      for (int x = 0; x < NXCD; ++x) {
+        // longest jobs first inside an XCD
+        std::stable_sort(per[x].begin(), per[x].end(), [](const Piece& a, const Piece& b) { return a.c > b.c; });
+        map_.task_begin[x] = (int)dev.size();
+        int64_t jb = 0;
+        for (const Piece& p : per[x]) {
+          GTask g = tasks[p.t];
+          g.job_begin = jb;
+          g.job_off = p.off;
+          g.njob = p.n;
+          jb += p.n;
+          dev.push_back(g);
+        }
+        map_.njobs[x] = jb;
+        map_.max_jobs = std::max(map_.max_jobs, jb);
+      }
+      map_.task_begin[NXCD] = (int)dev.size();
+      map_.shift = 0;
+      while ((map_.max_jobs >> map_.shift) > (int64_t(1) << 14)) ++map_.shift;
+      std::vector<int> bucket;
+      for (int x = 0; x < NXCD; ++x) {
+        map_.bucket_begin[x] = (int)bucket.size();
+        const int tb = map_.task_begin[x], te = map_.task_begin[x + 1];
+        const int64_t nb = (map_.njobs[x] >> map_.shift) + 1;
+        int ti = tb;
+        for (int64_t b = 0; b <= nb; ++b) {
+          const int64_t job = b << map_.shift;
+          while (ti + 1 < te && dev[ti + 1].job_begin <= job) ++ti;
+          bucket.push_back(te > tb ? ti : tb);
+        }
+      }
+      map_.bucket_begin[NXCD] = (int)bucket.size();
+      dbucket_ = (int*)dev_alloc(std::max<size_t>(1, bucket.size()) * sizeof(int));
+      dev_h2d(dbucket_, bucket.data(), bucket.size() * sizeof(int));
+    }
+    ntasks_dev_ = (int)dev.size();
+    if (dev.empty()) return;
+    dtasks_ = (GTask*)dev_alloc(dev.size() * sizeof(GTask));
+    dev_h2d(dtasks_, dev.data(), dev.size() * sizeof(GTask));
     dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
     if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
-    // bucket table: at most 2^16 buckets of 2^shift jobs
-    shift_ = 0;
-    while ((njobs >> shift_) > (int64_t(1) << 16)) ++shift_;
-    const int64_t nb = (njobs >> shift_) + 1;
-    std::vector<int> bucket((size_t)nb + 1);
-    size_t ti = 0;
-    for (int64_t b = 0; b <= nb; ++b) {
-      const int64_t job = b << shift_;
-      while (ti + 1 < tasks.size() && tasks[ti + 1].job_begin <= job) ++ti;
-      bucket[(size_t)b] = (int)ti;
-    }
-    dbucket_ = (int*)dev_alloc(bucket.size() * sizeof(int));
-    dev_h2d(dbucket_, bucket.data(), bucket.size() * sizeof(int));
   }
+  static int64_t jobs_of(const GTask& t) { return (int64_t)t.tiles_m * t.tiles_n * t.nbatch; }
   void run(DevTable& tab, const void* p0, void* p1, int elem, void* stream) {
     if (!dtasks_) upload();
     if (ntasks_dev_ == 0) return;
-    gemm_launch(dtasks_, ntasks_dev_, njobs, dcontribs_, dbucket_, shift_, tab.device(), p0, p1, elem, stream);
+    gemm_launch(dtasks_, ntasks_dev_, map_, dcontribs_, dbucket_, tab.device(), p0, p1, elem, stream);
   }
   void release() {
     dev_free(dtasks_);
@@ -163,7 +271,7 @@ class GemmList {
   GTask* dtasks_ = nullptr;
   GContrib* dcontribs_ = nullptr;
   int* dbucket_ = nullptr;
-  int shift_ = 0;
+  XcdMap map_{};
   int ntasks_dev_ = 0;
 };
 

@@ -98,6 +98,7 @@ __device__ __forceinline__ const T* bufp(int id, T* const* table, const T* p0, c
 // intersect the job's bucket of 2^shift consecutive jobs.
 __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const int* __restrict__ bucket,
                                          int shift, int64_t job) {
+  // bucket points at this XCD's table; task indices are global
   const int64_t b = job >> shift;
   int lo = bucket[b], hi = bucket[b + 1];
   while (lo < hi) {
@@ -115,7 +116,8 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
 // (32 per row, 8 rows per pass), otherwise r fastest (64 per row, 4 k per
 // pass); either way every thread owns 8 elements.
 struct Opnd {
-  const double* base;  // element (r_first, k_first) at k0 = 0
+  const double* origin;  // element (0, 0) of op(X): always a valid address
+  const double* base;    // element (r_first, k_first) at k0 = 0
   int64_t step_it;     // distance between a thread's consecutive elements
   int64_t step_k;      // distance of one BK tile
   int r_first, k_first;
@@ -140,6 +142,7 @@ __device__ __forceinline__ void opnd_setup(Opnd& o, const double* X, int64_t sr,
     o.k_inc = 4;
     o.step_it = 4 * sk;
   }
+  o.origin = X;
   o.base = X + (int64_t)(r0 + o.r_first) * sr + (int64_t)o.k_first * sk;
   o.step_k = (int64_t)BK * sk;
   o.rows = rows - r0;
@@ -147,18 +150,23 @@ __device__ __forceinline__ void opnd_setup(Opnd& o, const double* X, int64_t sr,
   o.scale = scale;
 }
 
-__device__ __forceinline__ void opnd_load(const Opnd& o, int k0, double (&v)[8]) {
+// Out-of-range elements load from the operand's origin (always valid) and
+// are zeroed by a select, so the eight loads issue back to back without
+// branches; nothing consumes them until the next LDS store.
+__device__ __forceinline__ void opnd_load(const Opnd& o, int k0, double (&v)[8], bool (&ok)[8]) {
   const double* p = o.base + (int64_t)(k0 / BK) * o.step_k;
 #pragma unroll
   for (int it = 0; it < 8; ++it) {
     const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
-    v[it] = (r < o.rows && k < o.K) ? p[it * o.step_it] * o.scale : 0.0;
+    ok[it] = (r < o.rows) & (k < o.K);
+    v[it] = *(ok[it] ? p + it * o.step_it : o.origin);
   }
 }
 
-__device__ __forceinline__ void opnd_store(const Opnd& o, const double (&v)[8], double (*L)[BM + LDP]) {
+__device__ __forceinline__ void opnd_store(const Opnd& o, const double (&v)[8], const bool (&ok)[8],
+                                           double (*L)[BM + LDP]) {
 #pragma unroll
-  for (int it = 0; it < 8; ++it) L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = v[it];
+  for (int it = 0; it < 8; ++it) L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = ok[it] ? v[it] * o.scale : 0.0;
 }
 
 // One step of the flattened (contribution, reduction index, k tile) sequence.
@@ -167,9 +175,9 @@ struct Step {
   int K;
 };
 
-__global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ tasks, int64_t njobs,
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ tasks, const XcdMap map,
                                                       const GContrib* __restrict__ contribs,
-                                                      const int* __restrict__ bucket, int shift,
+                                                      const int* __restrict__ bucket_all,
                                                       double* const* __restrict__ table, const double* p0,
                                                       const double* p1) {
   __shared__ double As[BK][BM + LDP];
@@ -177,9 +185,12 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int64_t job = blockIdx.x; job < njobs; job += gridDim.x) {
-    const GTask T = tasks[find_task(tasks, bucket, shift, job)];
-    const int64_t local = job - T.job_begin;
+  const int xcd = blockIdx.x % NXCD;
+  const int64_t njobs = map.njobs[xcd];
+  const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
+  for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) {
+    const GTask T = tasks[find_task(tasks, bucket, map.shift, job)];
+    const int64_t local = job - T.job_begin + T.job_off;
     const int tiles = T.tiles_m * T.tiles_n;
     const int64_t batch = local / tiles;
     const int tile = (int)(local - batch * tiles);
@@ -243,11 +254,12 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
       cur.K = contribs[cur.ci].K;
       setup(cur, oa, ob);
       double ra[8], rb[8];
-      opnd_load(oa, 0, ra);
-      opnd_load(ob, 0, rb);
+      bool ka[8], kb[8];
+      opnd_load(oa, 0, ra, ka);
+      opnd_load(ob, 0, rb, kb);
       for (;;) {
-        opnd_store(oa, ra, As);
-        opnd_store(ob, rb, Bs);
+        opnd_store(oa, ra, ka, As);
+        opnd_store(ob, rb, kb, Bs);
         __syncthreads();
         const int kend = (cur.K - cur.k0 < BK) ? cur.K - cur.k0 : BK;
         // advance and prefetch
@@ -267,10 +279,33 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
           }
         }
         if (more) {
-          opnd_load(oa, nxt.k0, ra);
-          opnd_load(ob, nxt.k0, rb);
+          opnd_load(oa, nxt.k0, ra, ka);
+          opnd_load(ob, nxt.k0, rb, kb);
         }
-        if (act00) {
+        if (act11 && kend == BK) {
+          // full tile: unrolled; the fragments of step kk+4 are read from
+          // LDS while the MFMAs of step kk run
+          double fa[2][2], fb[2][2];
+          fa[0][0] = As[lk][wm + lr];
+          fa[0][1] = As[lk][wm + 16 + lr];
+          fb[0][0] = Bs[lk][wn + lr];
+          fb[0][1] = Bs[lk][wn + 16 + lr];
+#pragma unroll
+          for (int s = 0; s < BK / 4; ++s) {
+            const int cb = s & 1, nb = cb ^ 1;
+            if (s + 1 < BK / 4) {
+              const int kn = 4 * (s + 1) + lk;
+              fa[nb][0] = As[kn][wm + lr];
+              fa[nb][1] = As[kn][wm + 16 + lr];
+              fb[nb][0] = Bs[kn][wn + lr];
+              fb[nb][1] = Bs[kn][wn + 16 + lr];
+            }
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][0], fb[cb][0], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][0], fb[cb][1], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][1], fb[cb][0], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][1], fb[cb][1], acc[1][1], 0, 0, 0);
+          }
+        } else if (act00) {
           for (int kk = 0; kk < kend; kk += 4) {
             double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
             double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
@@ -303,14 +338,14 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
   }
 }
 
-void gemm_launch(const GTask* tasks_dev, int ntasks, int64_t njobs, const GContrib* contribs_dev,
-                 const int* bucket_dev, int shift, void* const* table_dev, const void* p0, void* p1, int elem,
-                 void* stream) {
-  if (ntasks == 0 || njobs == 0) return;
-  int64_t grid = njobs < (1 << 22) ? njobs : (1 << 22);
+void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
+                 const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
+  if (ntasks == 0 || map.max_jobs == 0) return;
+  const int64_t per = map.max_jobs < (1 << 19) ? map.max_jobs : (1 << 19);
+  const int64_t grid = per * NXCD;
   if (elem == P_F64) {
-    hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, S(stream), tasks_dev, njobs,
-                       contribs_dev, bucket_dev, shift, (double* const*)table_dev, (const double*)p0,
+    hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, S(stream), tasks_dev, map,
+                       contribs_dev, bucket_dev, (double* const*)table_dev, (const double*)p0,
                        (const double*)p1);
   } else {
     throw Error(DMRG_EINVAL, "reduced-precision GEMM not built");

@@ -81,12 +81,13 @@ int nelec(int e) { return SITE_QN[e / 4].n() + SITE_QN[e % 4].n(); }
 }  // namespace dot
 
 Ops::~Ops() {
-  chunks.clear();
+  launches.clear();
   for (void* e : events) ev_destroy(e);
   if (L) L->free_dev();
   if (R) R->free_dev();
   for (auto& g : extra) g->free_dev();
-  dev_free(X);
+  dev_free(X[0]);
+  dev_free(X[1]);
   dev_free(X32);
   dev_free(psi32);
   dev_free(sig32);
@@ -694,16 +695,23 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
       }
     }
     if (!cur.empty()) chunk_pieces.push_back(cur);
+    // two scratch slots: the R-step of chunk i writes slot i%2 while the
+    // L-step of chunk i-1 (same launch) reads the other one
     O.Xbytes = (size_t)std::max<int64_t>(1, maxused) * sizeof(double);
-    O.X = (double*)dev_alloc(O.Xbytes);
-    O.Xbuf = tab.add(O.X);
+    for (int sl = 0; sl < 2; ++sl) {
+      O.X[sl] = (double*)dev_alloc(chunk_pieces.size() > (size_t)sl ? O.Xbytes : 256);
+      O.Xbuf[sl] = tab.add(O.X[sl]);
+    }
   }
+  const int nrchunks = (int)chunk_pieces.size();
   // identity-R families form an extra chunk without an R-step
   chunk_pieces.push_back({{-1, 0, 0, 0}});
 
-  std::vector<int> famL(O.fams.size());
+  std::vector<GemmList> Rl(chunk_pieces.size()), Ll(chunk_pieces.size());
   for (size_t ci = 0; ci < chunk_pieces.size(); ++ci) {
-    Chunk ch;
+    GemmList& rstep = Rl[ci];
+    GemmList& lstep = Ll[ci];
+    const int xb = (int)ci < nrchunks ? O.Xbuf[ci % 2] : -1;
     const auto& pcs = chunk_pieces[ci];
     // R-step
     for (const Piece& pc : pcs) {
@@ -715,12 +723,12 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
         int ir2 = -1;
         int sb = eff(r.g, r.t, b.ir, &ir2);
         const int dr2 = O.Rb.dim[ir2];
-        ch.rstep.begin(b.dl, dr2, pc.t1 - pc.t0, O.Xbuf, pc.xbase + r.xoff[bi], dr2, r.stride, false);
+        rstep.begin(b.dl, dr2, pc.t1 - pc.t0, xb, pc.xbase + r.xoff[bi], dr2, r.stride, false);
         GContrib c = make_contrib(b.dr, r.t ? 0 : GF_TRANS_B, 0, b.off, b.dr, r.g->buf,
                                   (int64_t)(r.base + pc.t0) * r.g->stride() + rl.off[sb], r.t ? dr2 : b.dr, 1.0);
         c.b_bstride = r.g->stride();
-        ch.rstep.add(c);
-        ch.rstep.end();
+        rstep.add(c);
+        rstep.end();
       }
     }
     // L-step: contributions grouped by output block
@@ -760,7 +768,7 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
               c.a_buf = 0;
             }
             if (r) {
-              c.b_buf = O.Xbuf;
+              c.b_buf = xb;
               c.b_off = pc.xbase + r->xoff[bi];
               c.ldb = ob.dr;
               c.b_rstride = r->stride;
@@ -778,21 +786,35 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
     for (int bo = 0; bo < nb; ++bo) {
       if (per_out[bo].empty()) continue;
       const PsiBlk& ob = O.blocks[bo];
-      ch.lstep.begin(ob.dl, ob.dr, 1, 1, ob.off, ob.dr, 0, true);
-      for (auto& c : per_out[bo]) ch.lstep.add(c);
-      ch.lstep.end();
+      lstep.begin(ob.dl, ob.dr, 1, 1, ob.off, ob.dr, 0, true);
+      for (auto& c : per_out[bo]) lstep.add(c);
+      lstep.end();
     }
-    O.flops_r += ch.rstep.flops;
-    O.flops_l += ch.lstep.flops;
-    O.ngemm_r += ch.rstep.ngemm;
-    O.ngemm_l += ch.lstep.ngemm;
-    ch.rstep.upload();
-    ch.lstep.upload();
-    ch.rstep.clear_host();
-    ch.lstep.clear_host();
-    O.chunks.push_back(std::move(ch));
+    O.flops_r += rstep.flops;
+    O.flops_l += lstep.flops;
+    O.ngemm_r += rstep.ngemm;
+    O.ngemm_l += lstep.ngemm;
   }
-  (void)famL;
+  // launches: [L(identity) + R(0)], [L(0) + R(1)], ..., [L(n-2) + R(n-1)], [L(n-1)];
+  // the L-step of one chunk shares a launch with the R-step of the next one
+  // so that the short R-step jobs fill the tail of the long L-step jobs.
+  {
+    const int n = nrchunks;
+    GemmList& Lid = Ll[n];
+    for (int i = 0; i <= n; ++i) {
+      std::vector<GemmList*> parts;
+      if (i == 0)
+        parts.push_back(&Lid);
+      else
+        parts.push_back(&Ll[i - 1]);
+      if (i < n) parts.push_back(&Rl[i]);
+      GemmList m = GemmList::merge_by_cost(parts);
+      if (m.tasks.empty()) continue;
+      m.upload();
+      m.clear_host();
+      O.launches.push_back(std::move(m));
+    }
+  }
   // operator memory kept for sigma
   auto gbytes = [](const Group& g) { return g.dev ? 8.0 * g.n() * (double)g.lay.size : 0.0; };
   for (auto& g : O.L->g) O.op_bytes += gbytes(g);
@@ -809,30 +831,17 @@ void sigma_run(Ops& O, const double* psi, double* sigma, int prec, void* stream)
   DMRG_CHECK(prec == P_F64, DMRG_EINVAL, "precision not available");
   k_fill(sigma, 0.0, O.npsi, stream);
   if (!O.profile) {
-    for (auto& ch : O.chunks) {
-      ch.rstep.run(*O.tab, psi, sigma, P_F64, stream);
-      ch.lstep.run(*O.tab, psi, sigma, P_F64, stream);
-    }
+    for (auto& l : O.launches) l.run(*O.tab, psi, sigma, P_F64, stream);
     return;
   }
-  const size_t need = 4 * O.chunks.size();
-  while (O.events.size() < need) O.events.push_back(ev_create());
-  size_t e = 0;
-  for (auto& ch : O.chunks) {
-    ev_record(O.events[e++], stream);
-    ch.rstep.run(*O.tab, psi, sigma, P_F64, stream);
-    ev_record(O.events[e++], stream);
-    ch.lstep.run(*O.tab, psi, sigma, P_F64, stream);
-    ev_record(O.events[e++], stream);
-    ++e;
+  while (O.events.size() < O.launches.size() + 1) O.events.push_back(ev_create());
+  ev_record(O.events[0], stream);
+  for (size_t i = 0; i < O.launches.size(); ++i) {
+    O.launches[i].run(*O.tab, psi, sigma, P_F64, stream);
+    ev_record(O.events[i + 1], stream);
   }
-  e = 0;
-  for (auto& ch : O.chunks) {
-    O.prof_r_ms += ev_elapsed_ms(O.events[e], O.events[e + 1]);
-    O.prof_l_ms += ev_elapsed_ms(O.events[e + 1], O.events[e + 2]);
-    O.prof_launches += (ch.rstep.empty() ? 0 : 1) + (ch.lstep.empty() ? 0 : 1);
-    e += 4;
-  }
+  for (size_t i = 0; i < O.launches.size(); ++i) O.prof_ms += ev_elapsed_ms(O.events[i], O.events[i + 1]);
+  O.prof_launches += (int64_t)O.launches.size();
   ++O.prof_calls;
 }
 

@@ -30,11 +30,6 @@ struct SFam {
   const char* tag = "";
 };
 
-struct Chunk {
-  GemmList rstep;   // X = psi . R^T   (Eq. sigmablk56)
-  GemmList lstep;   // sigma += c zeta L . X  (Eqs. sigmablk78 and sigmablk, fused)
-};
-
 struct Ops {
   int K = 0, Na = 0, Nb = 0, bond = 0, device = 0;
   double ecore = 0;
@@ -48,9 +43,11 @@ struct Ops {
   std::vector<int> blk_index;         // il*16*nR + e*nR + ir -> block or -1
   int64_t npsi = 0;
   std::vector<SFam> fams;
-  std::vector<Chunk> chunks;
-  double* X = nullptr;                // R-step scratch
-  int Xbuf = -1;
+  // GEMM launches of one sigma call: R-step X = psi . (O^R)^T (Eq. sigmablk56)
+  // and L-step sigma += c zeta D O^L . X (Eqs. sigmablk78, sigmablk fused)
+  std::vector<GemmList> launches;
+  double* X[2] = {nullptr, nullptr};  // R-step scratch (two slots)
+  int Xbuf[2] = {-1, -1};
   size_t Xbytes = 0;
   float* X32 = nullptr;               // reduced-precision scratch
   float* psi32 = nullptr;
@@ -62,7 +59,7 @@ struct Ops {
   // live kernel timing (HIP events around every GEMM launch of sigma)
   bool profile = false;
   std::vector<void*> events;
-  double prof_r_ms = 0, prof_l_ms = 0;
+  double prof_ms = 0;
   int64_t prof_launches = 0, prof_calls = 0;
 
   ~Ops();
