@@ -22,7 +22,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H·ψ sigma TFLOP/s & ms/call (K=73, D=2000); Davidson time to 1e-6 Eh"
-FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+# MI355X dense matrix peaks (TFLOP/s) per sigma precision; split-BF16 runs
+# three BF16 products per algorithmic product, so its peak in algorithmic
+# flops is a third of the BF16 rate.
+PEAKS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}
+PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 
 CONFIGS = {
     # name: (K, N_alpha, N_beta, D, bond, seed)
@@ -67,13 +71,64 @@ def cpu_baseline(ctx):
                        f"of that sample / oracle time; oracle operator build {t_build:.1f} s excluded")}
 
 
+def davidson_leg(ops, psi, mlp_path):
+    """Davidson time to 1e-6 Eh from the seeded start vector.
+
+    Solvers: FP32 sigma (FP64 polish) with the learned preconditioner, the same with
+    the diagonal preconditioner, and plain FP64 sigma with the diagonal one.  E_ref is
+    the energy of the first solver converged to ||r|| <= 1e-5 with FP64 sigma; its
+    time to E_ref + 1e-6 comes from its trace, the other two stop there.  The FP32
+    operator copies and the per-bond feature tables are built before the timed runs
+    (they belong to the operator build)."""
+    import torch
+    w = np.load(mlp_path).astype(np.float32)
+    y = torch.empty(len(psi), dtype=torch.float64, device="cuda")
+    x = torch.from_numpy(psi).cuda()
+    t = torch.empty_like(y)
+    ops.sigma(x.data_ptr(), y.data_ptr(), 1)                           # FP32 operator copies
+    ops.mlp_apply(w, x.data_ptr(), y.data_ptr(), 0.0, t.data_ptr())    # per-bond feature tables
+    torch.cuda.synchronize()
+    del t
+    out = {"start": "seeded Gaussian psi (the bench input)", "mlp_weights": os.path.relpath(mlp_path, ROOT)}
+    log("[bench] davidson fp32_mlp (reference run) ...")
+    x = torch.from_numpy(psi).cuda()
+    eref, st = ops.davidson(x.data_ptr(), trace=4000, precision=1, precond=1, mlp_weights=w,
+                            tol_residual=1e-5, max_iter=2000)
+    tr = st["trace"]
+    hit = np.nonzero((tr[:, 1] <= eref + 1e-6) & (tr[:, 3] == 0))[0]
+    out["E_ref"] = eref
+    out["fp32_mlp"] = {"seconds_to_1e-6": float(tr[hit[0], 0]), "iterations_to_1e-6": int(hit[0] + 1),
+                       "switch_iter": st["switch_iter"], "mlp_fallbacks": st["mlp_fallbacks"],
+                       "seconds_total": st["seconds"], "iterations_total": st["iterations"],
+                       "residual": st["residual"], "converged": st["converged"]}
+    log(f"[bench] davidson fp32_mlp: {out['fp32_mlp']}")
+    for name, kw in (("plain_fp64_diag", {}), ("fp32_diag", {"precision": 1})):
+        log(f"[bench] davidson {name} ...")
+        x = torch.from_numpy(psi).cuda()
+        e, st = ops.davidson(x.data_ptr(), e_ref=eref, e_tol=1e-6, stop_at_ref=1, max_iter=2000,
+                             tol_residual=1e-5, **kw)
+        out[name] = {"seconds_to_1e-6": st["seconds_to_ref"], "iterations_to_1e-6": st["iters_to_ref"],
+                     "fp64_sigma_calls": st["sigma_fp64"], "switch_iter": st["switch_iter"], "E-E_ref": e - eref}
+        log(f"[bench] davidson {name}: {out[name]}")
+    t0 = out["plain_fp64_diag"]["seconds_to_1e-6"]
+    t1 = out["fp32_mlp"]["seconds_to_1e-6"]
+    out["speedup_fp32_mlp_vs_plain"] = (t0 / t1) if (t0 and t0 > 0 and t1 and t1 > 0) else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="5", choices=sorted(CONFIGS))
+    ap.add_argument("--precision", default="fp64", choices=sorted(PREC_ID),
+                    help="arithmetic of the sigma contraction (psi and sigma stay binary64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
+    ap.add_argument("--davidson", action="store_true",
+                    help="also time Davidson to 1e-6 Eh (plain FP64+diagonal vs FP32+learned preconditioner)")
+    ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_02854_amd", "data", "precond_mlp.npy"),
+                    help="learned preconditioner weights for --davidson")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -110,15 +165,16 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("[bench] copy probe: 3 x 1 GiB device-to-device copies done")
+    prec = PREC_ID[args.precision]
     for i in range(args.warmup):
-        ops.sigma(x.data_ptr(), y.data_ptr())
+        ops.sigma(x.data_ptr(), y.data_ptr(), prec)
         torch.cuda.synchronize()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     ops.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        ops.sigma(x.data_ptr(), y.data_ptr())
+        ops.sigma(x.data_ptr(), y.data_ptr(), prec)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = ops.stats()
@@ -132,17 +188,20 @@ def main():
     out = {
         "metric": METRIC, "value": tflops, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": (f"two-dot DMRG sigma, K={K}, N={Na + Nb} ({Na}a,{Nb}b), Sz=0, D={D}, "
                                 f"dots at sites ({k + 1},{k + 2}) of 1..K, seeded integrals and MPS"),
                    "n_psi": int(st["n_psi"]), "psi_blocks": int(st["n_blocks"]), "terms": int(st["n_terms"]),
                    "gemms_per_call": int(st["n_rgemm"] + st["n_lgemm"]), "tflop_per_call": flops / 1e12,
                    "build_ops_s": t_build, "operator_GB": st["op_bytes"] / 1e9},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / FP64_PEAK_TFLOPS) if achieved else None, "traffic": None,
-                     "kernel": "gemm_f64_kernel", "kernel_ms_per_call": kern_ms,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS[args.precision], "unit": "TFLOP/s",
+                     "frac": (achieved / PEAKS[args.precision]) if achieved else None, "traffic": None,
+                     "kernel": f"gemm_kernel<{args.precision}>", "kernel_ms_per_call": kern_ms,
                      "launches_per_call": prof["prof_launches"] / max(1, prof["prof_sigma_calls"])},
     }
+    if args.davidson:
+        out["davidson"] = davidson_leg(ops, psi, args.mlp)
     if not args.no_cpu:
         log("[bench] cpu_baseline: oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(ctx)

@@ -107,11 +107,20 @@ typedef struct {
   int max_iter;            /* sigma calls, default 200 */
   int m_max;               /* subspace size before restart, 4..32, default 24 */
   int precision;           /* dmrg_precision of sigma in early iterations */
-  double switch_residual;  /* reduced precision used while ||r|| > switch_residual */
+  double switch_residual;  /* reduced precision used while ||r|| > max(switch_residual,
+                              f |theta|), f = 6e-6 (FP32) or 1.5e-5 (BF16x3): a few times the
+                              measured relative sigma error of the format */
   int precond;             /* 0 diagonal, 1 learned MLP (falls back to diagonal) */
-  const float* mlp_weights;/* host weights for precond == 1, layout in dmrg_mlp_size */
+  const float* mlp_weights;/* host weights for precond == 1 (dmrg_mlp_nweights floats) */
   double e_ref;            /* if finite: record time/iterations to reach e_ref + e_tol */
   double e_tol;
+  int stop_at_ref;         /* nonzero: stop at the first FP64 Ritz value <= e_ref + e_tol */
+  int stagnation;          /* switch to FP64 after this many consecutive reduced-precision
+                              iterations in which neither ||r|| fell below 0.9x its best nor
+                              theta fell by more than 1e-8 |theta| (default 4) */
+  double* trace;           /* optional host array [trace_cap][4]: per iteration (seconds since
+                              entry, Ritz value, ||r||_2, precision of the sigma behind it) */
+  int trace_cap;
 } dmrg_davidson_opts;
 
 typedef struct {
@@ -121,7 +130,10 @@ typedef struct {
   double seconds;          /* wall time of the call */
   double seconds_to_ref;   /* time to first Ritz value <= e_ref + e_tol (or -1) */
   int iters_to_ref;
-  int mlp_fallbacks;       /* iterations where the MLP correction was rejected */
+  int mlp_fallbacks;       /* iterations that used the diagonal correction although
+                              precond == 1 (the MLP step was judged by the FP64 residual) */
+  int switch_iter;         /* iteration at which FP64 sigma took over (-1: never reduced) */
+  int trace_len;           /* rows written to opts->trace */
 } dmrg_davidson_stats;
 
 /* Create a context on HIP device `device`, issuing work on `hip_stream`
@@ -174,6 +186,63 @@ int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi,
                   const dmrg_davidson_opts* opts, double* energy,
                   dmrg_davidson_stats* stats);
 void dmrg_davidson_default_opts(dmrg_davidson_opts* opts);
+
+/* ---- Learned Davidson preconditioner (an addition to the paper's method) ----
+ *
+ * A Davidson correction is t_i = g_i * d_i: d_i = r_i / (theta - H_ii) is the
+ * diagonal correction (|theta - H_ii| floored at 1e-8, sign kept) and the gain
+ * g_i = MLP(f_i) is evaluated per psi element by a network of FP32 layers
+ * DMRG_MLP_NFEAT -> ReLU(DMRG_MLP_HIDDEN) -> ReLU(DMRG_MLP_HIDDEN) -> 1.
+ * Features of element i, in block (il, n1, n2, ir) of a bond with dots at
+ * sites (k, k+1), theta the Ritz value and r the residual:
+ *   0      clamp((H_ii - theta) / s_h, -8, 8),  s_h = rms over i of (H_ii - theta)
+ *   1      asinh((H_ii - theta) / 0.01) / 8      (energies in Eh)
+ *   2      clamp(r_i / s_r, -8, 8),              s_r = rms over i of r_i
+ *   3      asinh(|r_i| / s_r) / 4
+ *   4, 5   (q_alpha, q_beta)(il) - (N_alpha, N_beta) * k / K, over sqrt(K)
+ *   6, 7   the right block's electrons (N - q(ir)) - N * (K - k - 2) / K, over sqrt(K)
+ *   8..11  one-hot n1;  12..15 one-hot n2
+ *   16, 17 log2(d_il) / 10, log2(d_ir) / 10
+ * Weights (host float arrays of dmrg_mlp_nweights() entries) in this order:
+ * W1[NFEAT][HIDDEN], b1[HIDDEN], W2[HIDDEN][HIDDEN], b2[HIDDEN], w3[HIDDEN], b3
+ * (W[in][out], row-major). */
+#define DMRG_MLP_NFEAT 18
+#define DMRG_MLP_HIDDEN 256
+
+/* Number of floats in a weight vector. */
+int dmrg_mlp_nweights(void);
+
+/* Seeded initial weights: uniform(-sqrt(6/fan_in), +) hidden layers, zero
+ * biases, w3 = 0 and b3 = 1, so that the initial network is the diagonal
+ * preconditioner (g = 1). */
+int dmrg_mlp_init(float* weights, uint64_t seed);
+
+/* Training pairs from one bond.  Runs FP64 Davidson with the diagonal
+ * preconditioner from psi0 (device, n_psi; not modified) for at most max_iter
+ * sigma calls and, at every iteration, draws per_iter element indices
+ * (seeded) and records for each: the features f_i, the diagonal correction
+ * d_i, and the target s*e_i, where e = psi_ref - x <x|psi_ref> is the part of
+ * the reference eigenvector psi_ref (device, normalised, sign aligned with x)
+ * orthogonal to the Ritz vector x, and s = <d,e>/<e,e> is the scale that best
+ * matches d.  Host outputs of capacity cap pairs: feat[cap][NFEAT], dcorr[cap],
+ * target[cap]; *n_out receives the number written.  Synchronous. */
+int dmrg_mlp_collect(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi0, const double* psi_ref,
+                     int max_iter, int per_iter, uint64_t seed, int64_t cap, float* feat,
+                     float* dcorr, float* target, int64_t* n_out);
+
+/* Fit the gains by Adam on the loss mean_i (g(f_i) d_i - target_i)^2 with the
+ * GPU training kernels.  Host inputs of n pairs (as written by
+ * dmrg_mlp_collect); weights (host) are read as the start point and
+ * overwritten with the result; loss_before/after (may be NULL) receive the
+ * loss over all n pairs.  Synchronous. */
+int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dcorr,
+                   const float* target, int epochs, int batch, float lr, uint64_t seed,
+                   float* weights, double* loss_before, double* loss_after);
+
+/* One preconditioner application on the device: t = g(f) * d for residual r
+ * and diagonal diag (device, n_psi each) at Ritz value theta; weights host. */
+int dmrg_mlp_apply(dmrg_ctx* ctx, const dmrg_ops* ops, const float* weights, const double* r,
+                   const double* diag, double theta, double* t);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,9 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ESHAPE", -3: "DMRG_ENOMEM",
 
 EXPORTS = ["dmrg_create", "dmrg_destroy", "dmrg_last_error", "dmrg_build_ops", "dmrg_ops_destroy",
            "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_sigma_batched",
-           "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile"]
+           "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile", "dmrg_mlp_nweights",
+           "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply"]
+MLP_NFEAT, MLP_HIDDEN = 18, 256
 
 
 class Integrals(C.Structure):
@@ -47,13 +49,15 @@ class Stats(C.Structure):
 class DavidsonOpts(C.Structure):
     _fields_ = [("tol_residual", C.c_double), ("max_iter", C.c_int), ("m_max", C.c_int),
                 ("precision", C.c_int), ("switch_residual", C.c_double), ("precond", C.c_int),
-                ("mlp_weights", C.POINTER(C.c_float)), ("e_ref", C.c_double), ("e_tol", C.c_double)]
+                ("mlp_weights", C.POINTER(C.c_float)), ("e_ref", C.c_double), ("e_tol", C.c_double),
+                ("stop_at_ref", C.c_int), ("stagnation", C.c_int),
+                ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int)]
 
 
 class DavidsonStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("sigma_fp64", C.c_int), ("residual", C.c_double),
                 ("seconds", C.c_double), ("seconds_to_ref", C.c_double), ("iters_to_ref", C.c_int),
-                ("mlp_fallbacks", C.c_int)]
+                ("mlp_fallbacks", C.c_int), ("switch_iter", C.c_int), ("trace_len", C.c_int)]
 
 
 def _p(a, ct):
@@ -84,6 +88,12 @@ def load(path=None):
     lib.dmrg_davidson_default_opts.argtypes = [C.POINTER(DavidsonOpts)]
     lib.dmrg_davidson_default_opts.restype = None
     lib.dmrg_profile.argtypes = [vp, C.c_int]
+    fp, dp = C.POINTER(C.c_float), C.POINTER(C.c_double)
+    lib.dmrg_mlp_nweights.argtypes = []
+    lib.dmrg_mlp_init.argtypes = [fp, C.c_uint64]
+    lib.dmrg_mlp_collect.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_uint64, C.c_int64, fp, fp, fp, i64p]
+    lib.dmrg_mlp_train.argtypes = [vp, C.c_int64, fp, fp, fp, C.c_int, C.c_int, C.c_float, C.c_uint64, fp, dp, dp]
+    lib.dmrg_mlp_apply.argtypes = [vp, vp, fp, vp, vp, C.c_double, vp]
     return lib
 
 
@@ -173,9 +183,15 @@ class Ops:
     def diag(self, out_ptr):
         self.ctx._check(self.ctx.lib.dmrg_diag(self.ctx.h, self.h, C.c_void_p(out_ptr)))
 
-    def davidson(self, psi_ptr, **kw):
+    def davidson(self, psi_ptr, trace=0, **kw):
+        """Lowest eigenpair in place; trace=N also returns the first N per-iteration rows
+        (seconds, theta, residual, precision) as out["trace"]."""
         o = DavidsonOpts()
         self.ctx.lib.dmrg_davidson_default_opts(C.byref(o))
+        tr = np.zeros((max(1, trace), 4)) if trace else None
+        if tr is not None:
+            o.trace = _p(tr, C.c_double)
+            o.trace_cap = int(trace)
         for k, v in kw.items():
             if k == "mlp_weights":
                 o.mlp_weights = v.ctypes.data_as(C.POINTER(C.c_float)) if v is not None else None
@@ -190,7 +206,46 @@ class Ops:
             self.ctx._check(rc)
         out = {k: getattr(st, k) for k, _ in DavidsonStats._fields_}
         out["converged"] = rc == 0
+        if tr is not None:
+            out["trace"] = tr[:st.trace_len].copy()
         return e.value, out
+
+
+    def mlp_collect(self, psi0_ptr, psi_ref_ptr, max_iter, per_iter, seed, cap):
+        """Training pairs of this bond (see dmrg_mlp_collect): (feat[n, NFEAT], dcorr[n], target[n])."""
+        feat = np.zeros((cap, MLP_NFEAT), np.float32)
+        dc = np.zeros(cap, np.float32)
+        tg = np.zeros(cap, np.float32)
+        n = C.c_int64()
+        self.ctx._check(self.ctx.lib.dmrg_mlp_collect(
+            self.ctx.h, self.h, C.c_void_p(psi0_ptr), C.c_void_p(psi_ref_ptr), int(max_iter), int(per_iter),
+            int(seed), int(cap), _p(feat, C.c_float), _p(dc, C.c_float), _p(tg, C.c_float), C.byref(n)))
+        k = n.value
+        return feat[:k], dc[:k], tg[:k]
+
+    def mlp_apply(self, weights, r_ptr, diag_ptr, theta, t_ptr):
+        w = np.ascontiguousarray(weights, np.float32)
+        self.ctx._check(self.ctx.lib.dmrg_mlp_apply(self.ctx.h, self.h, _p(w, C.c_float), C.c_void_p(r_ptr),
+                                                    C.c_void_p(diag_ptr), float(theta), C.c_void_p(t_ptr)))
+
+
+def mlp_init(lib, seed):
+    w = np.zeros(lib.dmrg_mlp_nweights(), np.float32)
+    lib.dmrg_mlp_init(_p(w, C.c_float), int(seed))
+    return w
+
+
+def mlp_train(ctx, feat, dcorr, target, weights, epochs=10, batch=4096, lr=1e-3, seed=0):
+    """Train in place on the GPU; returns (loss_before, loss_after)."""
+    feat = np.ascontiguousarray(feat, np.float32)
+    dcorr = np.ascontiguousarray(dcorr, np.float32)
+    target = np.ascontiguousarray(target, np.float32)
+    assert weights.dtype == np.float32 and weights.flags.c_contiguous
+    lb, la = C.c_double(), C.c_double()
+    ctx._check(ctx.lib.dmrg_mlp_train(ctx.h, len(dcorr), _p(feat, C.c_float), _p(dcorr, C.c_float),
+                                      _p(target, C.c_float), int(epochs), int(batch), float(lr), int(seed),
+                                      _p(weights, C.c_float), C.byref(lb), C.byref(la)))
+    return lb.value, la.value
 
 
 def sigma_batched(ctx, ops_list, psi_ptrs, sigma_ptrs, precision=FP64):

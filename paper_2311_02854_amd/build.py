@@ -21,8 +21,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 
-HIP_SOURCES = ["kernels.hip"]
-CXX_SOURCES = ["blocks.cpp", "ops.cpp", "davidson.cpp", "capi.cpp"]
+HIP_SOURCES = ["kernels.hip", "mlp.hip"]
+CXX_SOURCES = ["blocks.cpp", "ops.cpp", "davidson.cpp", "mlp.cpp", "capi.cpp"]
 
 
 def _run(cmd):

@@ -9,11 +9,6 @@
 #include "../../include/dmrg.h"
 #include "ops.h"
 
-namespace dmrg {
-int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* energy, dmrg_davidson_stats* st,
-                 void* stream);
-}
-
 struct dmrg_ctx {
   int device = 0;
   void* stream = nullptr;
@@ -188,7 +183,11 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts* o) {
   o->max_iter = 200;
   o->m_max = 24;
   o->precision = DMRG_FP64;
-  o->switch_residual = 1e-3;
+  o->switch_residual = 1e-4;
+  o->stop_at_ref = 0;
+  o->stagnation = 4;
+  o->trace = nullptr;
+  o->trace_cap = 0;
   o->precond = 0;
   o->mlp_weights = nullptr;
   o->e_ref = std::numeric_limits<double>::quiet_NaN();
@@ -206,11 +205,43 @@ int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi, const dmrg_da
   return guarded(ctx, [&] { return dmrg::davidson_run(*ops->p, psi, o, energy, stats, ctx->stream); });
 }
 
+int dmrg_mlp_nweights(void) { return dmrg::mlp_nweights(); }
+
+int dmrg_mlp_init(float* weights, uint64_t seed) {
+  if (!weights) return DMRG_EINVAL;
+  dmrg::mlp_init(weights, seed);
+  return DMRG_OK;
+}
+
+int dmrg_mlp_collect(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi0, const double* psi_ref, int max_iter,
+                     int per_iter, uint64_t seed, int64_t cap, float* feat, float* dcorr, float* target,
+                     int64_t* n_out) {
+  if (!ctx || !ops || !psi0 || !psi_ref || !feat || !dcorr || !target || !n_out) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    DMRG_CHECK(max_iter > 0 && per_iter > 0 && cap >= 0, DMRG_EINVAL, "max_iter, per_iter > 0 and cap >= 0 needed");
+    *n_out = dmrg::mlp_collect(*ops->p, psi0, psi_ref, max_iter, per_iter, seed, cap, feat, dcorr, target,
+                               ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dcorr, const float* target, int epochs,
+                   int batch, float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after) {
+  if (!ctx || !feat || !dcorr || !target || !weights) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    dmrg::mlp_train(n, feat, dcorr, target, epochs, batch, lr, seed, weights, loss_before, loss_after, ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_mlp_apply(dmrg_ctx* ctx, const dmrg_ops* ops, const float* weights, const double* r, const double* diag,
+                   double theta, double* t) {
+  if (!ctx || !ops || !weights || !r || !diag || !t) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    dmrg::mlp_apply_once(*ops->p, weights, r, diag, theta, t, ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
 }  // extern "C"
 
-namespace dmrg {
-void mlp_precondition(Ops&, const double*, const double*, const double*, double*, int* fallback, const float*,
-                      void*) {
-  *fallback = 1;
-}
-}  // namespace dmrg

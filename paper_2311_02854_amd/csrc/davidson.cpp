@@ -3,6 +3,14 @@
 // images W = H V, Gram-Schmidt, residuals and the small projected eigenproblem
 // are all FP64 on the GPU; the host keeps only the m x m projected matrix and
 // scalars needed for control flow.
+//
+// Mixed precision: while the residual is large, sigma may run in FP32 or
+// split-BF16 (the vectors and everything else stay FP64).  The solver switches
+// to FP64 sigma once the residual falls below switch_residual or stops
+// improving (its reduced-precision noise floor), restarting from the current
+// Ritz vector with an exact image; the energy it returns is always an FP64
+// Rayleigh quotient.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -10,9 +18,6 @@
 #include "ops.h"
 
 namespace dmrg {
-
-void mlp_precondition(Ops& O, const double* r, const double* diag, const double* theta, double* t, int* fallback,
-                      const float* weights, void* stream);
 
 namespace {
 struct DBuf {
@@ -30,10 +35,13 @@ double ddot(const double* x, const double* y, int64_t n, double* scratch, void* 
 }  // namespace
 
 int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* energy, dmrg_davidson_stats* st,
-                 void* stream) {
+                 void* stream, const DavidsonHook& hook) {
   const double t_start = wall_seconds();
   const int64_t n = O.npsi;
   const int mmax = std::max(4, std::min(32, opt.m_max));
+  DMRG_CHECK(opt.precision >= 0 && opt.precision <= 2, DMRG_EINVAL, "unknown precision");
+  DMRG_CHECK(opt.precond == 0 || (opt.precond == 1 && opt.mlp_weights), DMRG_EINVAL,
+             "precond 1 needs mlp_weights");
   DBuf V((size_t)mmax * n), W((size_t)mmax * n), dg(n), x(n), hx(n), r(n), t(n), xp(n), hxp(n), sm(4 * 32 * 32 + 64);
   double* dvals = sm.p;            // dots
   double* dG = sm.p + 64;          // projected matrix
@@ -45,6 +53,10 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   std::vector<double> G(32 * 32, 0.0), y(32, 0.0), yprev(32, 0.0), Z(32 * 32);
   int prec = opt.precision;
   const double floor_ = 1e-8;
+  const int stag_max = opt.stagnation > 0 ? opt.stagnation : 4;
+  // residual floor of reduced-precision sigma relative to |theta|: a few times
+  // the relative sigma error measured for each format
+  auto floor_rel = [](int p) { return p == P_F32 ? 6e-6 : (p == P_BF16X3 ? 1.5e-5 : 0.0); };
 
   auto sig = [&](const double* in, double* out, int p) { sigma_run(O, in, out, p, stream); };
   auto Vp = [&](int j) { return V.p + (int64_t)j * n; };
@@ -56,12 +68,14 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   k_copy(psi, Vp(0), n, stream);
   k_scale(Vp(0), 1.0 / nrm, n, stream);
   sig(Vp(0), Wp(0), prec);
-  int iters = 1, iters64 = (prec == P_F64) ? 1 : 0;
+  int iters = 1, iters64 = (prec == P_F64) ? 1 : 0, switch_iter = (prec == P_F64) ? -1 : 0;
   int m = 1;
-  double theta = 0, rn = 1e300;
-  bool have_prev = false, converged = false;
+  double theta = 0, rn = 1e300, best_rn = 1e300, prev_rn = 1e300, prev_theta = 1e300;
+  int stagnant = 0, ntrace = 0;
+  bool have_prev = false, converged = false, reached = false;
   double t_ref = -1;
-  int it_ref = -1, fallbacks = 0;
+  int it_ref = -1, fallbacks = 0, mlp_fail = 0;
+  bool used_mlp = false;
 
   auto rebuild_G = [&]() {  // full projected matrix of the current subspace
     for (int j = 0; j < m; ++j) {
@@ -79,7 +93,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       k_sub_lincomb(V.p, n, mcur, dvals, n, v, stream);
     }
     double nv = std::sqrt(ddot(v, v, n, dvals, stream));
-    if (nv > 0) k_scale(v, 1.0 / nv, n, stream);
+    if (nv > 0 && std::isfinite(nv)) k_scale(v, 1.0 / nv, n, stream);
     return nv;
   };
 
@@ -101,14 +115,33 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     k_lincomb(W.p, n, m, dy, n, hx.p, stream);
     k_copy(hx.p, r.p, n, stream);
     k_axpby(-theta, x.p, 1.0, r.p, n, stream);
+    prev_rn = rn;
     rn = std::sqrt(ddot(r.p, r.p, n, dvals, stream));
+    if (opt.trace && ntrace < opt.trace_cap) {
+      double* row = opt.trace + 4 * (int64_t)ntrace++;
+      row[0] = wall_seconds() - t_start;
+      row[1] = theta;
+      row[2] = rn;
+      row[3] = prec;
+    }
+    // the MLP step is judged by the FP64 residual it produced
+    if (used_mlp && !(rn < prev_rn)) ++mlp_fail;
     if (std::isfinite(opt.e_ref) && t_ref < 0 && prec == P_F64 && theta <= opt.e_ref + opt.e_tol) {
       t_ref = wall_seconds() - t_start;
       it_ref = iters;
+      reached = true;
     }
-    if (prec != P_F64 && rn <= opt.switch_residual) {
+    if (prec != P_F64) {
+      const bool improving = rn < 0.9 * best_rn || prev_theta - theta > 1e-8 * std::fabs(theta);
+      best_rn = std::min(best_rn, rn);
+      stagnant = improving ? 0 : stagnant + 1;
+    }
+    prev_theta = theta;
+    const double switch_at = std::max(opt.switch_residual, floor_rel(prec) * std::fabs(theta));
+    if (prec != P_F64 && (rn <= switch_at || stagnant >= stag_max)) {
       // switch to FP64 sigma: restart from the Ritz vector with an exact image
       prec = P_F64;
+      switch_iter = iters;
       k_copy(x.p, Vp(0), n, stream);
       double nx = std::sqrt(ddot(Vp(0), Vp(0), n, dvals, stream));
       k_scale(Vp(0), 1.0 / nx, n, stream);
@@ -117,23 +150,24 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       ++iters64;
       m = 1;
       have_prev = false;
+      used_mlp = false;
+      rn = 1e300;
       rebuild_G();
       continue;
     }
-    if ((rn <= opt.tol_residual && prec == P_F64) || iters >= opt.max_iter) {
+    if ((rn <= opt.tol_residual && prec == P_F64) || iters >= opt.max_iter || (reached && opt.stop_at_ref)) {
       converged = rn <= opt.tol_residual && prec == P_F64;
       break;
     }
     // correction vector
     dev_h2d(dth, &theta, sizeof(double));
-    bool used_mlp = false;
-    if (opt.precond == 1 && opt.mlp_weights) {
-      int fb = 0;
-      mlp_precondition(O, r.p, dg.p, dth, t.p, &fb, opt.mlp_weights, stream);
-      used_mlp = !fb;
-      fallbacks += fb;
-    }
-    if (!used_mlp) k_precond_diag(r.p, dg.p, dth, floor_, t.p, n, stream);
+    if (hook) hook(x.p, r.p, dg.p, dth, iters);
+    used_mlp = opt.precond == 1 && mlp_fail < 3;
+    if (used_mlp)
+      mlp_precondition(O, r.p, dg.p, dth, t.p, opt.mlp_weights, stream);
+    else
+      k_precond_diag(r.p, dg.p, dth, floor_, t.p, n, stream);
+    if (opt.precond == 1 && !used_mlp) ++fallbacks;
     if (m == mmax) {
       // restart with the current and the previous Ritz vectors
       int mnew = 1;
@@ -166,8 +200,10 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     have_prev = true;
     k_copy(t.p, Vp(m), n, stream);
     double nt = orth_normalize(Vp(m), m);
-    if (!(nt > 1e-14)) {
-      // correction collapsed: use the residual direction instead
+    if (!(nt > 1e-14) || !std::isfinite(nt)) {
+      // correction collapsed (or the model produced non-finite values): use
+      // the residual direction instead
+      if (used_mlp) ++mlp_fail;
       k_copy(r.p, Vp(m), n, stream);
       nt = orth_normalize(Vp(m), m);
       if (!(nt > 1e-14)) break;
@@ -185,6 +221,13 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   k_copy(x.p, psi, n, stream);
   double nx = std::sqrt(ddot(psi, psi, n, dvals, stream));
   k_scale(psi, 1.0 / nx, n, stream);
+  if (prec != P_F64) {
+    // stopped before the switch: report the FP64 Rayleigh quotient
+    sig(psi, hx.p, P_F64);
+    theta = ddot(psi, hx.p, n, dvals, stream);
+    ++iters;
+    ++iters64;
+  }
   dev_sync(stream);
   *energy = theta;
   if (st) {
@@ -195,8 +238,10 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     st->seconds_to_ref = t_ref;
     st->iters_to_ref = it_ref;
     st->mlp_fallbacks = fallbacks;
+    st->switch_iter = switch_iter;
+    st->trace_len = ntrace;
   }
-  return converged ? DMRG_OK : DMRG_ENOCONV;
+  return (converged || (reached && opt.stop_at_ref)) ? DMRG_OK : DMRG_ENOCONV;
 }
 
 }  // namespace dmrg

@@ -101,10 +101,27 @@ void k_gather_diag(const double* src, const int64_t* meta, int nblk, int64_t src
                    int64_t dst_stride, int nmem, double* dst, void* stream);
 // scale the per-member coefficient rows etc.: y[i] *= s
 void k_scale(double* y, double s, int64_t n, void* stream);
-// MLP preconditioner: features -> 2 hidden layers (ReLU) -> scalar gain g_i;
-// t_i = g_i * r_i / (theta - d_i).
-void k_mlp_precond(const float* feat, int nfeat, int64_t n, const float* w, int hidden,
-                   const double* r, const double* d, const double* theta, double floor_,
-                   double* t, void* stream);
+// --- learned preconditioner (mlp.hip) --------------------------------------
+// scales[0] = rms(diag - theta), scales[1] = rms(r); part holds 2*256 doubles
+void k_mlp_scales(const double* r, const double* diag, const double* theta, int64_t n, double* part,
+                  double* scales, void* stream);
+// out_i = g(f_i) * r_i / (theta - diag_i) with the MLP weights w (device)
+void k_mlp_apply(const float* w, const double* r, const double* diag, const double* theta, const double* scales,
+                 const int* blk, const float* stat, double floor_, double* out, int64_t n, void* stream);
+// features, diagonal correction and es*e at m sampled indices
+void k_mlp_gather_pairs(const int64_t* idx, int m, const double* r, const double* diag, const double* theta,
+                        const double* scales, const int* blk, const float* stat, const double* e, double es,
+                        double floor_, float* feat, float* dcorr, float* target, void* stream);
+// forward over rows of F[n][NFEAT]; a1/a2 (optional) receive the activations
+void k_mlp_train_fwd(const float* w, const float* F, int64_t n, float* a1, float* a2, float* g, void* stream);
+void k_mlp_bwd_out(const float* w, const float* g, const float* d, const float* y, const float* a2, int64_t n,
+                   float* dout, float* dz2, void* stream);
+void k_relu_mask(float* dz, const float* a, int64_t n, void* stream);
+void k_colsum(const float* X, const float* v, int64_t n, int ncol, float* out, void* stream);
+void k_sum_f(const float* x, int64_t n, float* out, void* stream);
+void k_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float c1,
+            float c2, float eps, void* stream);
+void k_sqerr(const float* g, const float* d, const float* y, int64_t n, float* out, void* stream);
+void k_gather_rows(const float* src, const int* perm, int64_t n, int width, float* dst, void* stream);
 
 }  // namespace dmrg

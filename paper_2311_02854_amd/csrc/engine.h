@@ -30,6 +30,7 @@ class DevTable {
     dirty_ = true;
   }
   void* get(int id) const { return ptrs_[id]; }
+  int size() const { return (int)ptrs_.size(); }
   void* const* device() {
     if (dirty_ || ptrs_.size() > cap_) {
       if (ptrs_.size() > cap_) {

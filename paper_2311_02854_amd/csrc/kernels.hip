@@ -3,9 +3,10 @@
 // The hot kernel is a grouped, batched GEMM driven by a task list: every
 // workgroup owns one 64x64 output tile of one task (output-stationary), loops
 // over the task's contributions (and, inside each, over a reduction index),
-// stages 64x16 / 16x64 operand tiles in LDS and accumulates in registers with
-// FP64 MFMA (v_mfma_f64_16x16x4f64).  Accumulation order is fixed, so results
-// are bitwise reproducible.
+// stages 64x32 / 32x64 operand tiles in LDS and accumulates in registers with
+// MFMA: FP64 (v_mfma_f64_16x16x4f64), FP32 (v_mfma_f32_16x16x4f32) or
+// split-BF16 (three v_mfma_f32_16x16x32_bf16 per step).  Accumulation order
+// is fixed, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -86,12 +87,65 @@ double wall_seconds() {
 
 // ---------------------------------------------------------------- GEMM
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, BK = 32, NT = 256, LDP = 2;
+constexpr int BM = 64, BN = 64, BK = 32, NT = 256;
 
-template <typename T>
-__device__ __forceinline__ const T* bufp(int id, T* const* table, const T* p0, const T* p1) {
-  return id == 0 ? p0 : (id == 1 ? p1 : table[id]);
+// Operand precision policies.  FP64 and FP32 stage op(A) and op(B) tiles in
+// LDS k-major ([k][row], rows contiguous) and feed 16x16x4 MFMAs one element
+// per lane.  BF16x3 reads FP32 operands, splits every value while staging into
+// hi = bf16(x) and lo = bf16(x - hi) (round to nearest even), stores them
+// row-major ([row][k], k contiguous) and accumulates hi*hi + hi*lo + lo*hi in
+// FP32 with 16x16x32 MFMAs.
+struct PolF64 {
+  using T = double;
+  using Acc = d4_t;
+  static constexpr bool split = false;
+  static constexpr int PAD = 2;
+  static constexpr int RL = 1, RV = 4;  // result row of element v in lane l: RL*(l/16) + RV*v
+};
+struct PolF32 {
+  using T = float;
+  using Acc = f4_t;
+  static constexpr bool split = false;
+  static constexpr int PAD = 4;
+  static constexpr int RL = 4, RV = 1;
+};
+struct PolBF3 {
+  using T = float;
+  using Acc = f4_t;
+  static constexpr bool split = true;
+  static constexpr int PAD = 8;
+  static constexpr int RL = 4, RV = 1;
+};
+
+template <class P, bool S = P::split>
+struct alignas(16) Smem {
+  typename P::T A[BK][BM + P::PAD];
+  typename P::T B[BK][BN + P::PAD];
+};
+template <class P>
+struct alignas(16) Smem<P, true> {
+  uint16_t Ah[BM][BK + P::PAD], Al[BM][BK + P::PAD];
+  uint16_t Bh[BN][BK + P::PAD], Bl[BN][BK + P::PAD];
+};
+
+__device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma32(bf8_t a, bf8_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// bf16 bits of x rounded to nearest, ties to even (finite x)
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
 
 // Task of a job: the bucket table narrows the search to the tasks that
@@ -115,19 +169,21 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
 // at X + r*sr + k*sk.  When k is contiguous (sk == 1) threads walk k fastest
 // (32 per row, 8 rows per pass), otherwise r fastest (64 per row, 4 k per
 // pass); either way every thread owns 8 elements.
+template <typename T>
 struct Opnd {
-  const double* origin;  // element (0, 0) of op(X): always a valid address
-  const double* base;    // element (r_first, k_first) at k0 = 0
-  int64_t step_it;     // distance between a thread's consecutive elements
-  int64_t step_k;      // distance of one BK tile
+  const T* origin;   // element (0, 0) of op(X): always a valid address
+  const T* base;     // element (r_first, k_first) at k0 = 0
+  int64_t step_it;   // distance between a thread's consecutive elements
+  int64_t step_k;    // distance of one BK tile
   int r_first, k_first;
-  int r_inc, k_inc;    // increments per element (one of them is 0)
-  int rows, K;         // valid extent (rows counted from the tile origin)
-  double scale;
+  int r_inc, k_inc;  // increments per element (one of them is 0)
+  int rows, K;       // valid extent (rows counted from the tile origin)
+  T scale;
 };
 
-__device__ __forceinline__ void opnd_setup(Opnd& o, const double* X, int64_t sr, int64_t sk, int r0, int rows,
-                                           int K, double scale) {
+template <typename T>
+__device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, int64_t sk, int r0, int rows,
+                                           int K, T scale) {
   const int tid = threadIdx.x;
   if (sk == 1) {
     o.r_first = tid >> 5;
@@ -153,8 +209,9 @@ __device__ __forceinline__ void opnd_setup(Opnd& o, const double* X, int64_t sr,
 // Out-of-range elements load from the operand's origin (always valid) and
 // are zeroed by a select, so the eight loads issue back to back without
 // branches; nothing consumes them until the next LDS store.
-__device__ __forceinline__ void opnd_load(const Opnd& o, int k0, double (&v)[8], bool (&ok)[8]) {
-  const double* p = o.base + (int64_t)(k0 / BK) * o.step_k;
+template <typename T>
+__device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[8], bool (&ok)[8]) {
+  const T* p = o.base + (int64_t)(k0 / BK) * o.step_k;
 #pragma unroll
   for (int it = 0; it < 8; ++it) {
     const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
@@ -163,10 +220,26 @@ __device__ __forceinline__ void opnd_load(const Opnd& o, int k0, double (&v)[8],
   }
 }
 
-__device__ __forceinline__ void opnd_store(const Opnd& o, const double (&v)[8], const bool (&ok)[8],
-                                           double (*L)[BM + LDP]) {
+template <typename T, int LD>
+__device__ __forceinline__ void opnd_store(const Opnd<T>& o, const T (&v)[8], const bool (&ok)[8],
+                                           T (*L)[LD]) {
 #pragma unroll
-  for (int it = 0; it < 8; ++it) L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = ok[it] ? v[it] * o.scale : 0.0;
+  for (int it = 0; it < 8; ++it)
+    L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = ok[it] ? v[it] * o.scale : T(0);
+}
+
+template <int LD>
+__device__ __forceinline__ void opnd_store_split(const Opnd<float>& o, const float (&v)[8], const bool (&ok)[8],
+                                                 uint16_t (*H)[LD], uint16_t (*Lo)[LD]) {
+#pragma unroll
+  for (int it = 0; it < 8; ++it) {
+    const float x = ok[it] ? v[it] * o.scale : 0.0f;
+    const uint16_t h = bf16_rne(x);
+    const uint16_t l = bf16_rne(x - __uint_as_float((uint32_t)h << 16));
+    const int r = o.r_first + it * o.r_inc, k = o.k_first + it * o.k_inc;
+    H[r][k] = h;
+    Lo[r][k] = l;
+  }
 }
 
 // One step of the flattened (contribution, reduction index, k tile) sequence.
@@ -175,54 +248,57 @@ struct Step {
   int K;
 };
 
-__global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ tasks, const XcdMap map,
-                                                      const GContrib* __restrict__ contribs,
-                                                      const int* __restrict__ bucket_all,
-                                                      double* const* __restrict__ table, const double* p0,
-                                                      const double* p1) {
-  __shared__ double As[BK][BM + LDP];
-  __shared__ double Bs[BK][BN + LDP];
+// Grouped GEMM over a task list (see device.h).  Operand buffers hold P::T;
+// the output is P::T except buffer 1 (p1), which is always binary64.
+template <class P>
+__global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ tasks, const XcdMap map,
+                                                  const GContrib* __restrict__ contribs,
+                                                  const int* __restrict__ bucket_all,
+                                                  typename P::T* const* __restrict__ table,
+                                                  const typename P::T* p0, double* p1) {
+  using T = typename P::T;
+  using Acc = typename P::Acc;
+  __shared__ Smem<P> sm;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
   const int xcd = blockIdx.x % NXCD;
   const int64_t njobs = map.njobs[xcd];
   const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
+  auto opp = [&](int id) -> const T* { return id == 0 ? p0 : (id == 1 ? (const T*)p1 : table[id]); };
   for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) {
-    const GTask T = tasks[find_task(tasks, bucket, map.shift, job)];
-    const int64_t local = job - T.job_begin + T.job_off;
-    const int tiles = T.tiles_m * T.tiles_n;
+    const GTask Tk = tasks[find_task(tasks, bucket, map.shift, job)];
+    const int64_t local = job - Tk.job_begin + Tk.job_off;
+    const int tiles = Tk.tiles_m * Tk.tiles_n;
     const int64_t batch = local / tiles;
     const int tile = (int)(local - batch * tiles);
-    const int m0 = (tile / T.tiles_n) * BM, n0 = (tile % T.tiles_n) * BN;
-    const int mrem = T.M - m0 - wm, nrem = T.N - n0 - wn;
+    const int m0 = (tile / Tk.tiles_n) * BM, n0 = (tile % Tk.tiles_n) * BN;
+    const int mrem = Tk.M - m0 - wm, nrem = Tk.N - n0 - wn;
     const bool act00 = mrem > 0 && nrem > 0, act01 = mrem > 0 && nrem > 16;
     const bool act10 = mrem > 16 && nrem > 0, act11 = mrem > 16 && nrem > 16;
-    d4_t acc[2][2];
+    Acc acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+      for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
     // identity contributions: acc += alpha op(B)  (M == K)
-    for (int ci = T.contrib_begin; ci < T.contrib_end; ++ci) {
+    for (int ci = Tk.contrib_begin; ci < Tk.contrib_end; ++ci) {
       const GContrib& Cb = contribs[ci];
       if (!(Cb.flags & GF_IDENT_A)) continue;
       const bool tb = Cb.flags & GF_TRANS_B;
       for (int t = 0; t < Cb.nred; ++t) {
-        const double* B = bufp<double>(Cb.b_buf, table, p0, p1) + Cb.b_off + batch * Cb.b_bstride +
-                          (int64_t)t * Cb.b_rstride;
-        double alpha = Cb.alpha;
-        if (Cb.s_buf >= 0)
-          alpha *= bufp<double>(Cb.s_buf, table, p0, p1)[Cb.s_off + batch * Cb.s_bstride + (int64_t)t * Cb.s_rstride];
+        const T* B = opp(Cb.b_buf) + Cb.b_off + batch * Cb.b_bstride + (int64_t)t * Cb.b_rstride;
+        T alpha = (T)Cb.alpha;
+        if (Cb.s_buf >= 0) alpha *= opp(Cb.s_buf)[Cb.s_off + batch * Cb.s_bstride + (int64_t)t * Cb.s_rstride];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
           for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              int r = m0 + wm + mi * 16 + lk + 4 * v, c = n0 + wn + ni * 16 + lr;
-              if (r < T.M && c < T.N)
+              int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
+              if (r < Tk.M && c < Tk.N)
                 acc[mi][ni][v] += alpha * (tb ? B[(int64_t)c * Cb.ldb + r] : B[(int64_t)r * Cb.ldb + c]);
             }
       }
@@ -231,35 +307,37 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
     // MFMA contributions, software pipelined: the next tile is fetched into
     // registers while the current one is multiplied out of LDS.
     auto first_from = [&](int ci) {
-      while (ci < T.contrib_end && (contribs[ci].flags & GF_IDENT_A)) ++ci;
+      while (ci < Tk.contrib_end && (contribs[ci].flags & GF_IDENT_A)) ++ci;
       return ci;
     };
-    auto setup = [&](const Step& s, Opnd& oa, Opnd& ob) {
+    auto setup = [&](const Step& s, Opnd<T>& oa, Opnd<T>& ob) {
       const GContrib& Cb = contribs[s.ci];
-      const double* A = bufp<double>(Cb.a_buf, table, p0, p1) + Cb.a_off + batch * Cb.a_bstride +
-                        (int64_t)s.t * Cb.a_rstride;
-      const double* B = bufp<double>(Cb.b_buf, table, p0, p1) + Cb.b_off + batch * Cb.b_bstride +
-                        (int64_t)s.t * Cb.b_rstride;
-      double alpha = Cb.alpha;
-      if (Cb.s_buf >= 0)
-        alpha *= bufp<double>(Cb.s_buf, table, p0, p1)[Cb.s_off + batch * Cb.s_bstride + (int64_t)s.t * Cb.s_rstride];
+      const T* A = opp(Cb.a_buf) + Cb.a_off + batch * Cb.a_bstride + (int64_t)s.t * Cb.a_rstride;
+      const T* B = opp(Cb.b_buf) + Cb.b_off + batch * Cb.b_bstride + (int64_t)s.t * Cb.b_rstride;
+      T alpha = (T)Cb.alpha;
+      if (Cb.s_buf >= 0) alpha *= opp(Cb.s_buf)[Cb.s_off + batch * Cb.s_bstride + (int64_t)s.t * Cb.s_rstride];
       const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
       // op(A)(m, k): stored M x K (lda) or K x M;  op(B)(k, n) seen as (n, k)
-      opnd_setup(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, T.M, Cb.K, alpha);
-      opnd_setup(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, T.N, Cb.K, 1.0);
+      opnd_setup<T>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
+      opnd_setup<T>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
     };
-    Step cur{first_from(T.contrib_begin), 0, 0, 0};
-    if (cur.ci < T.contrib_end) {
-      Opnd oa, ob;
+    Step cur{first_from(Tk.contrib_begin), 0, 0, 0};
+    if (cur.ci < Tk.contrib_end) {
+      Opnd<T> oa, ob;
       cur.K = contribs[cur.ci].K;
       setup(cur, oa, ob);
-      double ra[8], rb[8];
+      T ra[8], rb[8];
       bool ka[8], kb[8];
       opnd_load(oa, 0, ra, ka);
       opnd_load(ob, 0, rb, kb);
       for (;;) {
-        opnd_store(oa, ra, ka, As);
-        opnd_store(ob, rb, kb, Bs);
+        if constexpr (P::split) {
+          opnd_store_split(oa, ra, ka, sm.Ah, sm.Al);
+          opnd_store_split(ob, rb, kb, sm.Bh, sm.Bl);
+        } else {
+          opnd_store(oa, ra, ka, sm.A);
+          opnd_store(ob, rb, kb, sm.B);
+        }
         __syncthreads();
         const int kend = (cur.K - cur.k0 < BK) ? cur.K - cur.k0 : BK;
         // advance and prefetch
@@ -271,7 +349,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
           if (++nxt.t >= contribs[nxt.ci].nred) {
             nxt.t = 0;
             nxt.ci = first_from(nxt.ci + 1);
-            more = nxt.ci < T.contrib_end;
+            more = nxt.ci < Tk.contrib_end;
           }
           if (more) {
             nxt.K = contribs[nxt.ci].K;
@@ -282,37 +360,60 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
           opnd_load(oa, nxt.k0, ra, ka);
           opnd_load(ob, nxt.k0, rb, kb);
         }
-        if (act11 && kend == BK) {
+        if constexpr (P::split) {
+          // one 16x16x32 step covers the whole k tile (entries past K are 0)
+          if (act00) {
+            bf8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              ah[i] = *reinterpret_cast<const bf8_t*>(&sm.Ah[wm + i * 16 + lr][8 * lk]);
+              al[i] = *reinterpret_cast<const bf8_t*>(&sm.Al[wm + i * 16 + lr][8 * lk]);
+              bh[i] = *reinterpret_cast<const bf8_t*>(&sm.Bh[wn + i * 16 + lr][8 * lk]);
+              bl[i] = *reinterpret_cast<const bf8_t*>(&sm.Bl[wn + i * 16 + lr][8 * lk]);
+            }
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+              for (int ni = 0; ni < 2; ++ni) {
+                const bool on = (mi ? act10 : act00) && (ni ? (mi ? act11 : act01) : true);
+                if (on) {
+                  acc[mi][ni] = mfma32(al[mi], bh[ni], acc[mi][ni]);
+                  acc[mi][ni] = mfma32(ah[mi], bl[ni], acc[mi][ni]);
+                  acc[mi][ni] = mfma32(ah[mi], bh[ni], acc[mi][ni]);
+                }
+              }
+          }
+        } else if (act11 && kend == BK) {
           // full tile: unrolled; the fragments of step kk+4 are read from
           // LDS while the MFMAs of step kk run
-          double fa[2][2], fb[2][2];
-          fa[0][0] = As[lk][wm + lr];
-          fa[0][1] = As[lk][wm + 16 + lr];
-          fb[0][0] = Bs[lk][wn + lr];
-          fb[0][1] = Bs[lk][wn + 16 + lr];
+          T fa[2][2], fb[2][2];
+          fa[0][0] = sm.A[lk][wm + lr];
+          fa[0][1] = sm.A[lk][wm + 16 + lr];
+          fb[0][0] = sm.B[lk][wn + lr];
+          fb[0][1] = sm.B[lk][wn + 16 + lr];
 #pragma unroll
           for (int s = 0; s < BK / 4; ++s) {
             const int cb = s & 1, nb = cb ^ 1;
             if (s + 1 < BK / 4) {
               const int kn = 4 * (s + 1) + lk;
-              fa[nb][0] = As[kn][wm + lr];
-              fa[nb][1] = As[kn][wm + 16 + lr];
-              fb[nb][0] = Bs[kn][wn + lr];
-              fb[nb][1] = Bs[kn][wn + 16 + lr];
+              fa[nb][0] = sm.A[kn][wm + lr];
+              fa[nb][1] = sm.A[kn][wm + 16 + lr];
+              fb[nb][0] = sm.B[kn][wn + lr];
+              fb[nb][1] = sm.B[kn][wn + 16 + lr];
             }
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][0], fb[cb][0], acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][0], fb[cb][1], acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][1], fb[cb][0], acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[cb][1], fb[cb][1], acc[1][1], 0, 0, 0);
+            acc[0][0] = mfma4(fa[cb][0], fb[cb][0], acc[0][0]);
+            acc[0][1] = mfma4(fa[cb][0], fb[cb][1], acc[0][1]);
+            acc[1][0] = mfma4(fa[cb][1], fb[cb][0], acc[1][0]);
+            acc[1][1] = mfma4(fa[cb][1], fb[cb][1], acc[1][1]);
           }
         } else if (act00) {
           for (int kk = 0; kk < kend; kk += 4) {
-            double a0 = As[kk + lk][wm + lr], a1 = As[kk + lk][wm + 16 + lr];
-            double b0 = Bs[kk + lk][wn + lr], b1 = Bs[kk + lk][wn + 16 + lr];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            if (act01) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            if (act10) acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            if (act11) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            T a0 = sm.A[kk + lk][wm + lr], a1 = sm.A[kk + lk][wm + 16 + lr];
+            T b0 = sm.B[kk + lk][wn + lr], b1 = sm.B[kk + lk][wn + 16 + lr];
+            acc[0][0] = mfma4(a0, b0, acc[0][0]);
+            if (act01) acc[0][1] = mfma4(a0, b1, acc[0][1]);
+            if (act10) acc[1][0] = mfma4(a1, b0, acc[1][0]);
+            if (act11) acc[1][1] = mfma4(a1, b1, acc[1][1]);
           }
         }
         __syncthreads();
@@ -320,21 +421,27 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(const GTask* __restrict__ 
         cur = nxt;
       }
     }
-    double* Cp = const_cast<double*>(bufp<double>(T.c_buf, table, p0, p1)) + T.c_off + batch * T.c_bstride;
+    // result element v of lane l in sub-tile (mi, ni): row RL*(l/16) + RV*v, column l%16
+    auto store = [&](auto* Cp) {
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          int r = m0 + wm + mi * 16 + lk + 4 * v, c = n0 + wn + ni * 16 + lr;
-          if (r < T.M && c < T.N) {
-            double val = acc[mi][ni][v];
-            double* dst = Cp + (int64_t)r * T.ldc + c;
-            if (T.accumulate) val += *dst;
-            *dst = val;
+          for (int v = 0; v < 4; ++v) {
+            int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
+            if (r < Tk.M && c < Tk.N) {
+              auto* dst = Cp + (int64_t)r * Tk.ldc + c;
+              auto val = (decltype(*dst + 0))acc[mi][ni][v];
+              if (Tk.accumulate) val += *dst;
+              *dst = val;
+            }
           }
-        }
+    };
+    if (Tk.c_buf == 1)
+      store(p1 + Tk.c_off + batch * Tk.c_bstride);
+    else
+      store(table[Tk.c_buf] + Tk.c_off + batch * Tk.c_bstride);
   }
 }
 
@@ -342,13 +449,18 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
                  const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
   if (ntasks == 0 || map.max_jobs == 0) return;
   const int64_t per = map.max_jobs < (1 << 19) ? map.max_jobs : (1 << 19);
-  const int64_t grid = per * NXCD;
+  const dim3 grid((unsigned)(per * NXCD)), block(NT);
   if (elem == P_F64) {
-    hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)grid), dim3(NT), 0, S(stream), tasks_dev, map,
-                       contribs_dev, bucket_dev, (double* const*)table_dev, (const double*)p0,
-                       (const double*)p1);
+    hipLaunchKernelGGL(gemm_kernel<PolF64>, grid, block, 0, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+                       (double* const*)table_dev, (const double*)p0, (double*)p1);
+  } else if (elem == P_F32) {
+    hipLaunchKernelGGL(gemm_kernel<PolF32>, grid, block, 0, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+                       (float* const*)table_dev, (const float*)p0, (double*)p1);
+  } else if (elem == P_BF16X3) {
+    hipLaunchKernelGGL(gemm_kernel<PolBF3>, grid, block, 0, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+                       (float* const*)table_dev, (const float*)p0, (double*)p1);
   } else {
-    throw Error(DMRG_EINVAL, "reduced-precision GEMM not built");
+    throw Error(DMRG_EINVAL, "unknown GEMM precision");
   }
   dev_check("gemm_launch");
 }
@@ -598,11 +710,6 @@ void k_gather_diag(const double* src, const int64_t* meta, int nblk, int64_t sst
   unsigned gx = nblk < 1024 ? nblk : 1024;
   hipLaunchKernelGGL(gather_diag_kernel, dim3(gx, nmem), dim3(64), 0, S(s), src, meta, nblk, sstride, dstride, dst);
   dev_check("k_gather_diag");
-}
-
-void k_mlp_precond(const float*, int, int64_t, const float*, int, const double*, const double*, const double*,
-                   double, double*, void*) {
-  throw Error(DMRG_EINVAL, "MLP preconditioner not built");
 }
 
 }  // namespace dmrg

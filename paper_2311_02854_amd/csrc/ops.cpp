@@ -88,9 +88,14 @@ Ops::~Ops() {
   for (auto& g : extra) g->free_dev();
   dev_free(X[0]);
   dev_free(X[1]);
-  dev_free(X32);
+  dev_free(X32[0]);
+  dev_free(X32[1]);
   dev_free(psi32);
-  dev_free(sig32);
+  dev_free(mlp_blk);
+  dev_free(mlp_stat);
+  dev_free(mlp_part);
+  dev_free(mlp_scales);
+  dev_free(mlp_w);
 }
 
 namespace {
@@ -801,6 +806,7 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
   {
     const int n = nrchunks;
     GemmList& Lid = Ll[n];
+    std::set<int> bufs;
     for (int i = 0; i <= n; ++i) {
       std::vector<GemmList*> parts;
       if (i == 0)
@@ -810,10 +816,19 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
       if (i < n) parts.push_back(&Rl[i]);
       GemmList m = GemmList::merge_by_cost(parts);
       if (m.tasks.empty()) continue;
+      for (const GTask& t : m.tasks) bufs.insert(t.c_buf);
+      for (const GContrib& c : m.contribs) {
+        if (!(c.flags & GF_IDENT_A)) bufs.insert(c.a_buf);
+        bufs.insert(c.b_buf);
+        if (c.s_buf >= 0) bufs.insert(c.s_buf);
+        DMRG_CHECK(c.b_buf != 1 && ((c.flags & GF_IDENT_A) || c.a_buf != 1), DMRG_EINTERNAL,
+                   "sigma plan reads its output buffer");
+      }
       m.upload();
       m.clear_host();
       O.launches.push_back(std::move(m));
     }
+    O.sigma_bufs.assign(bufs.begin(), bufs.end());
   }
   // operator memory kept for sigma
   auto gbytes = [](const Group& g) { return g.dev ? 8.0 * g.n() * (double)g.lay.size : 0.0; };
@@ -828,16 +843,24 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
 
 // ----------------------------------------------------------------------------
 void sigma_run(Ops& O, const double* psi, double* sigma, int prec, void* stream) {
-  DMRG_CHECK(prec == P_F64, DMRG_EINVAL, "precision not available");
+  DMRG_CHECK(prec == P_F64 || prec == P_F32 || prec == P_BF16X3, DMRG_EINVAL, "unknown precision");
+  DevTable* tab = O.tab.get();
+  const void* p0 = psi;
+  if (prec != P_F64) {
+    make_reduced_copies(O, stream);
+    k_d2f(psi, O.psi32, O.npsi, stream);
+    tab = O.tab32.get();
+    p0 = O.psi32;
+  }
   k_fill(sigma, 0.0, O.npsi, stream);
   if (!O.profile) {
-    for (auto& l : O.launches) l.run(*O.tab, psi, sigma, P_F64, stream);
+    for (auto& l : O.launches) l.run(*tab, p0, sigma, prec, stream);
     return;
   }
   while (O.events.size() < O.launches.size() + 1) O.events.push_back(ev_create());
   ev_record(O.events[0], stream);
   for (size_t i = 0; i < O.launches.size(); ++i) {
-    O.launches[i].run(*O.tab, psi, sigma, P_F64, stream);
+    O.launches[i].run(*tab, p0, sigma, prec, stream);
     ev_record(O.events[i + 1], stream);
   }
   for (size_t i = 0; i < O.launches.size(); ++i) O.prof_ms += ev_elapsed_ms(O.events[i], O.events[i + 1]);
@@ -918,6 +941,38 @@ void diag_run(Ops& O, double* diag, void* stream) {
   }
 }
 
-void make_reduced_copies(Ops&, void*) {}
+void make_reduced_copies(Ops& O, void* stream) {
+  if (O.tab32) return;
+  auto t32 = std::make_unique<DevTable>();
+  while (t32->size() < O.tab->size()) t32->add(nullptr);
+  std::set<int> need(O.sigma_bufs.begin(), O.sigma_bufs.end());
+  need.erase(0);
+  need.erase(1);
+  auto convert = [&](Group& g) {
+    if (!g.dev || !need.count(g.buf)) return;
+    const int64_t n = (int64_t)g.n() * g.lay.size;
+    if (!g.dev32) {
+      g.dev32 = (float*)dev_alloc(sizeof(float) * (size_t)std::max<int64_t>(1, n));
+      k_d2f(g.dev, g.dev32, n, stream);
+    }
+    t32->set(g.buf, g.dev32);
+    O.op_bytes32 += 4.0 * (double)n;
+    need.erase(g.buf);
+  };
+  for (auto& g : O.L->g) convert(g);
+  for (auto& g : O.R->g) convert(g);
+  for (auto& g : O.extra) convert(*g);
+  for (int sl = 0; sl < 2; ++sl) {
+    if (!need.count(O.Xbuf[sl])) continue;
+    O.X32[sl] = (float*)dev_alloc(std::max<size_t>(256, O.Xbytes / 2));
+    t32->set(O.Xbuf[sl], O.X32[sl]);
+    need.erase(O.Xbuf[sl]);
+  }
+  DMRG_CHECK(need.empty(), DMRG_EINTERNAL, "sigma plan reads a buffer without a reduced-precision copy");
+  O.psi32 = (float*)dev_alloc(sizeof(float) * (size_t)O.npsi);
+  dev_sync(stream);
+  O.tab32 = std::move(t32);
+}
+
 
 }  // namespace dmrg

@@ -1,5 +1,6 @@
 // One bond's device-resident operators and its sigma plan.
 #pragma once
+#include <functional>
 #include <memory>
 #include <string>
 #include <vector>
@@ -49,10 +50,20 @@ struct Ops {
   double* X[2] = {nullptr, nullptr};  // R-step scratch (two slots)
   int Xbuf[2] = {-1, -1};
   size_t Xbytes = 0;
-  float* X32 = nullptr;               // reduced-precision scratch
+  // reduced precision (FP32 / BF16x3): FP32 copies of every buffer the plan
+  // reads, under the same buffer ids in a second pointer table
+  std::vector<int> sigma_bufs;        // buffer ids read or written by the sigma launches
+  std::unique_ptr<DevTable> tab32;    // null until the first reduced-precision call
+  float* X32[2] = {nullptr, nullptr};
   float* psi32 = nullptr;
-  float* sig32 = nullptr;
-  bool have32 = false;
+  double op_bytes32 = 0;
+  // learned preconditioner (built on first use)
+  int* mlp_blk = nullptr;             // psi element -> block
+  float* mlp_stat = nullptr;          // per block: static features
+  double* mlp_part = nullptr;
+  double* mlp_scales = nullptr;
+  float* mlp_w = nullptr;
+  std::vector<float> mlp_w_host;
   // stats
   double flops_r = 0, flops_l = 0, build_seconds = 0, build_flops = 0, op_bytes = 0;
   int64_t ngemm_r = 0, ngemm_l = 0, nterms = 0;
@@ -79,6 +90,27 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
 
 void sigma_run(Ops& ops, const double* psi, double* sigma, int prec, void* stream);
 void diag_run(Ops& ops, double* diag, void* stream);
+// FP32 copies of the sigma operators (idempotent; synchronous)
 void make_reduced_copies(Ops& ops, void* stream);
+
+// Called by Davidson every iteration with the Ritz vector x, residual r,
+// diag(H) and the Ritz value (device scalar), before the correction step.
+using DavidsonHook = std::function<void(const double* x, const double* r, const double* diag,
+                                        const double* theta_dev, int iter)>;
+int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* energy, dmrg_davidson_stats* st,
+                 void* stream, const DavidsonHook& hook = DavidsonHook());
+
+// learned preconditioner (mlp.cpp)
+int mlp_nweights();
+void mlp_init(float* w, uint64_t seed);
+void mlp_prepare(Ops& O, void* stream);
+void mlp_precondition(Ops& O, const double* r, const double* diag, const double* theta_dev, double* t,
+                      const float* weights, void* stream);
+void mlp_apply_once(Ops& O, const float* weights, const double* r, const double* diag, double theta, double* t,
+                    void* stream);
+int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_iter, int per_iter, uint64_t seed,
+                    int64_t cap, float* feat, float* dcorr, float* target, void* stream);
+void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* target, int epochs, int batch,
+               float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after, void* stream);
 
 }  // namespace dmrg

@@ -1,0 +1,124 @@
+"""Train the learned Davidson preconditioner and store its weights.
+
+Training pairs come from Davidson runs of the method itself on the seeded
+synthetic workloads K8 (N=8, D=64), K24 (N=24, D=1000, several bonds) and K36
+(N=36, D=3000, mid-chain): every iteration of an FP64 diagonal-preconditioned
+run contributes sampled (features, diagonal correction, ideal correction)
+triples (dmrg_mlp_collect); the reference eigenvector behind the ideal
+correction is the converged Davidson vector of the same problem (FP32 sigma,
+then FP64 to ||r|| <= 1e-6).  The
+network is fit by the library's GPU training kernels (dmrg_mlp_train) and
+checked on a held-out bond by the number of Davidson iterations to 1e-6 Eh.
+
+    python -m paper_2311_02854_amd.train_precond [--out PATH] [--quick]
+
+Writes PATH (float32 .npy, dmrg_mlp_nweights() entries) and PATH.json.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+DEFAULT_OUT = os.path.join(HERE, "data", "precond_mlp.npy")
+
+# (K, N_alpha, N_beta, D, bond, seed)
+TRAIN = [(8, 4, 4, 64, 3, 1)] + [(24, 12, 12, 1000, b, 2) for b in (5, 8, 11, 14, 17)] + \
+        [(36, 18, 18, 3000, 17, 3)]
+HOLDOUT = (24, 12, 12, 1000, 13, 2)
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def problem(ctx, K, Na, Nb, D, k, seed):
+    import synth
+    ints = synth.make_integrals(K, 1000 + seed)
+    mps = synth.make_mps(K, Na, Nb, D, k, 3000 + seed)
+    psi = synth.make_psi(mps, 2000 + seed)
+    return ctx.build_ops(ints, mps), psi
+
+
+def reference(ops, psi, tol=1e-6):
+    """Converged eigenvector: FP32 sigma until its noise floor, then FP64 to ||r|| <= tol."""
+    import torch
+    x = torch.from_numpy(psi).cuda()
+    e, st = ops.davidson(x.data_ptr(), tol_residual=tol, max_iter=600, precision=1)
+    return x, e, st
+
+
+def main():
+    import torch
+    from paper_2311_02854_amd import binding as B
+    from paper_2311_02854_amd import gpu_context
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("--quick", action="store_true", help="K8 and one K24 bond only")
+    ap.add_argument("--iters", type=int, default=80, help="Davidson iterations sampled per problem")
+    ap.add_argument("--per-iter", type=int, default=2048)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    args = ap.parse_args()
+
+    ctx = gpu_context(0)
+    train = TRAIN[:2] if args.quick else TRAIN
+    feats, dcs, tgs, meta = [], [], [], []
+    for spec in train:
+        t0 = time.time()
+        log(f"[train] K={spec[0]} D={spec[3]} bond={spec[4]}: building operators")
+        ops, psi = problem(ctx, *spec)
+        log(f"[train]   reference eigenvector ({time.time() - t0:.1f}s)")
+        xref, eref, st = reference(ops, psi)
+        log(f"[train]   collecting pairs ({time.time() - t0:.1f}s)")
+        x0 = torch.from_numpy(psi).cuda()
+        f, d, y = ops.mlp_collect(x0.data_ptr(), xref.data_ptr(), args.iters, args.per_iter,
+                                  seed=len(meta) + 1, cap=args.iters * args.per_iter)
+        feats.append(f)
+        dcs.append(d)
+        tgs.append(y)
+        meta.append({"problem": spec, "n_psi": ops.n_psi, "E_ref": eref, "ref_iters": st["iterations"],
+                     "pairs": int(len(d))})
+        log(f"[train] K={spec[0]} D={spec[3]} bond={spec[4]}: n_psi={ops.n_psi} E={eref:.8f} "
+            f"({st['iterations']} it) pairs={len(d)} {time.time() - t0:.1f}s")
+        del ops
+    F = np.concatenate(feats)
+    D = np.concatenate(dcs)
+    Y = np.concatenate(tgs)
+    w = B.mlp_init(ctx.lib, 12345)
+    t0 = time.time()
+    lb, la = B.mlp_train(ctx, F, D, Y, w, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=7)
+    log(f"[train] {len(D)} pairs, loss {lb:.4e} -> {la:.4e} ({time.time() - t0:.1f}s)")
+    log("[train] held-out bond")
+
+    # held-out bond: Davidson iterations to 1e-6 Eh, diagonal vs learned
+    ops, psi = problem(ctx, *HOLDOUT)
+    _, eref, _ = reference(ops, psi)
+    val = {}
+    for name, kw in (("diag", {}), ("mlp", {"precond": 1, "mlp_weights": w})):
+        x = torch.from_numpy(psi).cuda()
+        e, st = ops.davidson(x.data_ptr(), tol_residual=1e-7, max_iter=600, e_ref=eref, e_tol=1e-6,
+                             stop_at_ref=1, **kw)
+        val[name] = {"iters_to_1e-6": st["iters_to_ref"], "seconds_to_1e-6": st["seconds_to_ref"],
+                     "iterations": st["iterations"], "E-E_ref": e - eref, "fallbacks": st["mlp_fallbacks"]}
+        log(f"[train] held-out K24 bond {HOLDOUT[4]} {name}: {val[name]}")
+
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.save(args.out, w)
+    with open(args.out + ".json", "w") as fh:
+        json.dump({"nweights": int(len(w)), "train": meta, "pairs": int(len(D)), "loss_before": lb,
+                   "loss_after": la, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+                   "iters_per_problem": args.iters, "per_iter": args.per_iter,
+                   "holdout": {"problem": HOLDOUT, **val}}, fh, indent=1)
+    log(f"[train] wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+"""GPU learned Davidson preconditioner: inference against a NumPy evaluation of
+the documented features and network, training, and Davidson with the model.
+
+The preconditioner is not part of the paper (parity unpinned there): these
+tests pin the kernels to their documented definition (include/dmrg.h), and
+the eigenvalue to the FP64 oracle / FCI.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fock
+
+pytestmark = pytest.mark.gpu
+
+NF, HD = 18, 256
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2311_02854_amd import gpu_context
+    return gpu_context(0)
+
+
+def problem(K, Na, Nb, D, k, seed):
+    ints = synth.make_integrals(K, 1000 + seed)
+    mps = synth.make_mps(K, Na, Nb, D, k, 3000 + seed)
+    psi = synth.make_psi(mps, 2000 + seed)
+    return ints, mps, psi
+
+
+def np_features(ops, mps, r, dg, theta):
+    K, k = mps.K, mps.k
+    Na, Nb = mps.Na, mps.Nb
+    dh = dg - theta
+    sh = np.sqrt(np.mean(dh * dh)) + 1e-300
+    sr = np.sqrt(np.mean(r * r)) + 1e-300
+    F = np.zeros((len(r), NF))
+    F[:, 0] = np.clip(dh / sh, -8, 8)
+    F[:, 1] = np.arcsinh(dh / 0.01) / 8
+    F[:, 2] = np.clip(r / sr, -8, 8)
+    F[:, 3] = np.arcsinh(np.abs(r) / sr) / 4
+    secL, secR = mps.sectors[k], mps.sectors[k + 2]
+    rK = np.sqrt(K)
+    for b, (il, n1, n2, ir, dl, dr) in enumerate(ops.blk_meta):
+        sl = slice(ops.blk_off[b], ops.blk_off[b] + dl * dr)
+        qa, qb = secL[il][0], secL[il][1]
+        ra, rb = secR[ir][0], secR[ir][1]
+        F[sl, 4] = (qa - Na * k / K) / rK
+        F[sl, 5] = (qb - Nb * k / K) / rK
+        F[sl, 6] = ((Na - ra) - Na * (K - k - 2) / K) / rK
+        F[sl, 7] = ((Nb - rb) - Nb * (K - k - 2) / K) / rK
+        F[sl, 8 + n1] = 1
+        F[sl, 12 + n2] = 1
+        F[sl, 16] = np.log2(dl) / 10
+        F[sl, 17] = np.log2(dr) / 10
+    return F
+
+
+def np_gain(w, F):
+    o = 0
+    W1 = w[o:o + NF * HD].reshape(NF, HD); o += NF * HD
+    b1 = w[o:o + HD]; o += HD
+    W2 = w[o:o + HD * HD].reshape(HD, HD); o += HD * HD
+    b2 = w[o:o + HD]; o += HD
+    w3 = w[o:o + HD]; o += HD
+    b3 = w[o]
+    a1 = np.maximum(F @ W1 + b1, 0)
+    a2 = np.maximum(a1 @ W2 + b2, 0)
+    return a2 @ w3 + b3
+
+
+def diag_corr(r, dg, theta):
+    den = theta - dg
+    small = np.abs(den) < 1e-8
+    den = np.where(small, np.where(den < 0, -1e-8, 1e-8), den)
+    return r / den
+
+
+def test_mlp_init_is_diagonal_preconditioner(ctx):
+    import torch
+    from paper_2311_02854_amd import binding as B
+    ints, mps, psi = problem(8, 4, 4, 64, 3, 1)
+    ops = ctx.build_ops(ints, mps)
+    w = B.mlp_init(ctx.lib, 7)
+    dg = torch.empty(ops.n_psi, dtype=torch.float64, device="cuda")
+    ops.diag(dg.data_ptr())
+    r = torch.from_numpy(np.random.default_rng(1).normal(size=ops.n_psi)).cuda()
+    t = torch.empty_like(r)
+    theta = float(dg.min().item()) - 0.3
+    ops.mlp_apply(w, r.data_ptr(), dg.data_ptr(), theta, t.data_ptr())
+    torch.cuda.synchronize()
+    ref = diag_corr(r.cpu().numpy(), dg.cpu().numpy(), theta)
+    assert np.array_equal(t.cpu().numpy(), ref)
+
+
+def test_mlp_forward_matches_numpy(ctx):
+    import torch
+    from paper_2311_02854_amd import binding as B
+    ints, mps, psi = problem(10, 5, 5, 64, 4, 3)
+    ops = ctx.build_ops(ints, mps)
+    w = B.mlp_init(ctx.lib, 11)
+    rng = np.random.default_rng(5)
+    w[-HD - 1:-1] = rng.normal(0, 0.05, HD).astype(np.float32)      # w3
+    w[NF * HD:NF * HD + HD] = rng.normal(0, 0.1, HD).astype(np.float32)  # b1
+    w[-1] = 0.3
+    dg = torch.empty(ops.n_psi, dtype=torch.float64, device="cuda")
+    ops.diag(dg.data_ptr())
+    rn = rng.normal(size=ops.n_psi)
+    r = torch.from_numpy(rn).cuda()
+    t = torch.empty_like(r)
+    dgn = dg.cpu().numpy()
+    theta = float(np.median(dgn))     # crosses the diagonal: exercises the floor and both signs
+    ops.mlp_apply(w, r.data_ptr(), dg.data_ptr(), theta, t.data_ptr())
+    torch.cuda.synchronize()
+    F = np_features(ops, mps, rn, dgn, theta)
+    g = np_gain(w.astype(np.float64), F)
+    ref = g * diag_corr(rn, dgn, theta)
+    got = t.cpu().numpy()
+    # FP32 network: compare gains (relative to the gain scale)
+    gg = got / diag_corr(rn, dgn, theta)
+    err = np.abs(gg - g).max() / np.abs(g).max()
+    print(f"gain max rel err {err:.2e}")
+    assert err < 1e-4, err
+    assert np.isfinite(got).all() and np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-4
+
+
+def test_mlp_collect_and_train_reduce_loss(ctx):
+    import torch
+    from paper_2311_02854_amd import binding as B
+    ints, mps, psi = problem(8, 4, 4, 64, 3, 1)
+    ops = ctx.build_ops(ints, mps)
+    x = torch.from_numpy(psi).cuda()
+    e, st = ops.davidson(x.data_ptr(), tol_residual=1e-9, max_iter=400)
+    assert st["converged"]
+    x0 = torch.from_numpy(psi).cuda()
+    feat, dc, tg = ops.mlp_collect(x0.data_ptr(), x.data_ptr(), 40, 512, 3, 40 * 512)
+    assert len(dc) > 1000 and np.isfinite(feat).all() and np.isfinite(dc).all() and np.isfinite(tg).all()
+    assert np.array_equal(x0.cpu().numpy(), psi)        # psi0 not modified
+    w = B.mlp_init(ctx.lib, 5)
+    lb, la = B.mlp_train(ctx, feat, dc, tg, w, epochs=4, batch=1024, lr=1e-3, seed=1)
+    # at initialisation g = 1: the loss is the diagonal preconditioner's
+    ref_lb = float(np.mean((dc.astype(np.float64) - tg) ** 2))
+    print(f"loss before {lb:.4e} (numpy {ref_lb:.4e}) after {la:.4e}")
+    assert abs(lb - ref_lb) <= 1e-3 * ref_lb
+    assert la < lb
+
+
+def test_davidson_with_mlp_reaches_fci(ctx):
+    import torch
+    from paper_2311_02854_amd import binding as B
+    ints, mps, psi = problem(8, 4, 4, 64, 3, 1)
+    ops = ctx.build_ops(ints, mps)
+    H, _ = fock.hamiltonian(ints["h"], ints["eri"], 4, 4)
+    efci = fock.fci_energy(H)
+    w = B.mlp_init(ctx.lib, 9)
+    x = torch.from_numpy(psi).cuda()
+    e, st = ops.davidson(x.data_ptr(), tol_residual=1e-7, max_iter=400, precond=1, mlp_weights=w,
+                         precision=1, switch_residual=1e-4)
+    print(f"E-EFCI={e - efci:.2e} iters={st['iterations']} fallbacks={st['mlp_fallbacks']}")
+    assert st["converged"]
+    assert abs(e - efci) < 1e-9
