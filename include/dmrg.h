@@ -25,6 +25,7 @@
 #ifndef DMRG_H
 #define DMRG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -142,13 +143,20 @@ int dmrg_create(dmrg_ctx** ctx, int device, void* hip_stream);
 void dmrg_destroy(dmrg_ctx* ctx);
 const char* dmrg_last_error(const dmrg_ctx* ctx);
 
+/* Scratch budgets of dmrg_build_ops (0 selects the default). */
+typedef struct {
+  size_t x_budget_bytes;   /* each of the two R-step scratch slots of sigma (default 4 GiB):
+                              a smaller budget splits sigma into more launches */
+  size_t t_budget_bytes;   /* renormalization scratch per growth step (default 2 GiB) */
+} dmrg_build_opts;
+
 /* Build the renormalized operators of the two-dot problem at mps->bond by
  * growing the left block over sites 0..bond-1 and the right block over sites
  * K-1..bond+2 (Eq. Renorm on the GPU), then form the complementary operators
- * and intermediates and plan sigma.  Synchronous.  *out is owned by the caller
- * and released with dmrg_ops_destroy. */
+ * and intermediates and plan sigma.  Synchronous.  opts may be NULL.  *out is
+ * owned by the caller and released with dmrg_ops_destroy. */
 int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mps,
-                   dmrg_ops** out);
+                   const dmrg_build_opts* opts, dmrg_ops** out);
 void dmrg_ops_destroy(dmrg_ops* ops);
 
 /* psi layout: blocks (il, n1, n2, ir), il a sector of bond `bond`, ir the sector
@@ -175,9 +183,29 @@ int dmrg_sigma(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi, double* si
 /* Diagonal H_ii of the two-dot Hamiltonian in the psi layout (device output). */
 int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag);
 
-/* sigma for nprob independent problems in one fused launch sequence. */
+/* sigma for nprob independent problems (each its own dmrg_ops, psi and sigma
+ * device buffers, psi/sigma as in dmrg_sigma) in one fused launch sequence:
+ * launch j runs launch j of every problem's plan, with all problems' tiles in
+ * one XCD schedule; the sequence is captured once into a HIP graph and
+ * replayed while the ops and pointer sets stay the same (the context keeps
+ * the last plan; changing the set rebuilds it).  The first call with a new set
+ * also autotunes the launch shapes (a few extra sigma sequences).  Results
+ * equal those of dmrg_sigma per problem bit for bit.  flags: DMRG_BATCH_EAGER
+ * issues the launches directly instead of through the graph; DMRG_BATCH_NO_TUNE
+ * keeps the default shapes.  Asynchronous on the context stream (the first
+ * call and calls with new pointers synchronise it). */
+#define DMRG_BATCH_EAGER 1
+#define DMRG_BATCH_NO_TUNE 2
 int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops,
-                       const double* const* psi, double* const* sigma, int precision);
+                       const double* const* psi, double* const* sigma, int precision, int flags);
+
+/* Autotune the launch shapes of dmrg_sigma in one precision: every tile shape
+ * (64x64, 32x32, 64x32, 32x64 outputs per workgroup) and then a persistent
+ * grid are timed per launch on one sigma call each, and the fastest is kept
+ * for later calls (results do not change).  Synchronous.  ms_default /
+ * ms_tuned (may be NULL) receive the summed launch times with the default
+ * and the chosen shapes. */
+int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_default, double* ms_tuned);
 
 /* Lowest eigenpair.  psi (device, n_psi) holds the initial guess and receives
  * the normalised eigenvector; *energy its FP64 Rayleigh quotient (ecore

@@ -21,7 +21,7 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ESHAPE", -3: "DMRG_ENOMEM",
 EXPORTS = ["dmrg_create", "dmrg_destroy", "dmrg_last_error", "dmrg_build_ops", "dmrg_ops_destroy",
            "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_sigma_batched",
            "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile", "dmrg_mlp_nweights",
-           "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply"]
+           "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply", "dmrg_autotune"]
 MLP_NFEAT, MLP_HIDDEN = 18, 256
 
 
@@ -35,6 +35,10 @@ class Mps(C.Structure):
                 ("nsec", C.POINTER(C.c_int)), ("sec_qn", C.POINTER(C.c_int)),
                 ("sec_dim", C.POINTER(C.c_int)), ("blk_off", C.POINTER(C.c_int64)),
                 ("data", C.POINTER(C.c_double))]
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("x_budget_bytes", C.c_size_t), ("t_budget_bytes", C.c_size_t)]
 
 
 class Stats(C.Structure):
@@ -75,14 +79,15 @@ def load(path=None):
     lib.dmrg_destroy.restype = None
     lib.dmrg_last_error.argtypes = [vp]
     lib.dmrg_last_error.restype = C.c_char_p
-    lib.dmrg_build_ops.argtypes = [vp, C.POINTER(Integrals), C.POINTER(Mps), C.POINTER(vp)]
+    lib.dmrg_build_ops.argtypes = [vp, C.POINTER(Integrals), C.POINTER(Mps), C.POINTER(BuildOpts), C.POINTER(vp)]
     lib.dmrg_ops_destroy.argtypes = [vp]
     lib.dmrg_ops_destroy.restype = None
     lib.dmrg_ops_layout.argtypes = [vp, i64p, i64p, C.POINTER(C.c_int), i64p]
     lib.dmrg_ops_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.dmrg_sigma.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.dmrg_diag.argtypes = [vp, vp, vp]
-    lib.dmrg_sigma_batched.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int]
+    lib.dmrg_sigma_batched.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_int]
+    lib.dmrg_autotune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.dmrg_davidson.argtypes = [vp, vp, vp, C.POINTER(DavidsonOpts), C.POINTER(C.c_double),
                                   C.POINTER(DavidsonStats)]
     lib.dmrg_davidson_default_opts.argtypes = [C.POINTER(DavidsonOpts)]
@@ -128,8 +133,9 @@ class Context:
         except Exception:
             pass
 
-    def build_ops(self, ints, mps):
-        """ints: dict(K, h, eri, ecore); mps: synth.SiteMPS (host arrays, copied)."""
+    def build_ops(self, ints, mps, x_budget=0, t_budget=0):
+        """ints: dict(K, h, eri, ecore); mps: synth.SiteMPS (host arrays, copied); budgets in bytes
+        (0: library default)."""
         h = np.ascontiguousarray(ints["h"], dtype=np.float64)
         eri = np.ascontiguousarray(ints["eri"], dtype=np.float64)
         I = Integrals(int(ints["K"]), _p(h, C.c_double), _p(eri, C.c_double), float(ints.get("ecore", 0.0)))
@@ -141,7 +147,8 @@ class Context:
         M = Mps(mps.K, mps.Na, mps.Nb, mps.k, _p(nsec, C.c_int), _p(qn, C.c_int), _p(dim, C.c_int),
                 _p(off, C.c_int64), _p(data, C.c_double))
         out = C.c_void_p()
-        self._check(self.lib.dmrg_build_ops(self.h, C.byref(I), C.byref(M), C.byref(out)))
+        bo = BuildOpts(int(x_budget), int(t_budget))
+        self._check(self.lib.dmrg_build_ops(self.h, C.byref(I), C.byref(M), C.byref(bo), C.byref(out)))
         return Ops(self, out)
 
 
@@ -172,6 +179,12 @@ class Ops:
         s = Stats()
         self.ctx._check(self.ctx.lib.dmrg_ops_stats(self.h, C.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def autotune(self, precision=FP64):
+        """Pick launch shapes for dmrg_sigma; returns (ms_default, ms_tuned) of one call."""
+        a, b = C.c_double(), C.c_double()
+        self.ctx._check(self.ctx.lib.dmrg_autotune(self.ctx.h, self.h, int(precision), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def profile(self, enable=True):
         self.ctx._check(self.ctx.lib.dmrg_profile(self.h, int(enable)))
@@ -248,11 +261,14 @@ def mlp_train(ctx, feat, dcorr, target, weights, epochs=10, batch=4096, lr=1e-3,
     return lb.value, la.value
 
 
-def sigma_batched(ctx, ops_list, psi_ptrs, sigma_ptrs, precision=FP64):
+BATCH_EAGER, BATCH_NO_TUNE = 1, 2
+
+
+def sigma_batched(ctx, ops_list, psi_ptrs, sigma_ptrs, precision=FP64, flags=0):
     n = len(ops_list)
     arr = C.c_void_p * n
     ctx._check(ctx.lib.dmrg_sigma_batched(ctx.h, n, arr(*[o.h for o in ops_list]), arr(*psi_ptrs),
-                                          arr(*sigma_ptrs), int(precision)))
+                                          arr(*sigma_ptrs), int(precision), int(flags)))
 
 
 def nan():

@@ -22,7 +22,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 
 HIP_SOURCES = ["kernels.hip", "mlp.hip"]
-CXX_SOURCES = ["blocks.cpp", "ops.cpp", "davidson.cpp", "mlp.cpp", "capi.cpp"]
+CXX_SOURCES = ["blocks.cpp", "ops.cpp", "davidson.cpp", "mlp.cpp", "batch.cpp", "capi.cpp"]
 
 
 def _run(cmd):

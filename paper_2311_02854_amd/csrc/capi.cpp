@@ -7,12 +7,14 @@
 #include <string>
 
 #include "../../include/dmrg.h"
+#include "batch.h"
 #include "ops.h"
 
 struct dmrg_ctx {
   int device = 0;
   void* stream = nullptr;
   std::string err;
+  std::unique_ptr<dmrg::BatchPlan> batch;  // last fused multi-problem plan
 };
 
 struct dmrg_ops {
@@ -63,7 +65,8 @@ void dmrg_destroy(dmrg_ctx* ctx) { delete ctx; }
 
 const char* dmrg_last_error(const dmrg_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mps, dmrg_ops** out) {
+int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mps, const dmrg_build_opts* opts,
+                   dmrg_ops** out) {
   if (!ctx || !ints || !mps || !out) return DMRG_EINVAL;
   *out = nullptr;
   return guarded(ctx, [&] {
@@ -76,6 +79,10 @@ int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mp
     I.eri.assign(ints->eri, ints->eri + (size_t)K * K * K * K);
     I.ecore = ints->ecore;
     dmrg::BuildOptions opt;
+    if (opts && opts->x_budget_bytes) opt.x_budget = opts->x_budget_bytes;
+    if (opts && opts->t_budget_bytes) opt.t_budget = opts->t_budget_bytes;
+    DMRG_CHECK(opt.x_budget >= (size_t(1) << 20) && opt.t_budget >= (size_t(1) << 20), DMRG_EINVAL,
+               "scratch budgets below 1 MiB");
     auto o = dmrg::build_ops(I, K, mps->n_alpha, mps->n_beta, mps->bond, mps->nsec, mps->sec_qn, mps->sec_dim,
                              mps->blk_off, mps->data, ctx->stream, opt);
     o->device = ctx->device;
@@ -165,13 +172,40 @@ int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag) {
 }
 
 int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops, const double* const* psi,
-                       double* const* sigma, int precision) {
+                       double* const* sigma, int precision, int flags) {
   if (!ctx || nprob < 0 || (nprob > 0 && (!ops || !psi || !sigma))) return DMRG_EINVAL;
+  if (nprob == 0) return DMRG_OK;
   return guarded(ctx, [&] {
+    DMRG_CHECK(precision >= 0 && precision <= 2, DMRG_EINVAL, "unknown precision");
+    DMRG_CHECK((flags & ~(DMRG_BATCH_EAGER | DMRG_BATCH_NO_TUNE)) == 0, DMRG_EINVAL, "unknown flags");
+    std::vector<dmrg::Ops*> v;
     for (int i = 0; i < nprob; ++i) {
       DMRG_CHECK(ops[i] && psi[i] && sigma[i], DMRG_EINVAL, "null problem entry");
-      dmrg::sigma_run(*ops[i]->p, psi[i], sigma[i], precision, ctx->stream);
+      for (int j = 0; j < i; ++j)
+        DMRG_CHECK(ops[j] != ops[i] && sigma[j] != sigma[i], DMRG_EINVAL,
+                   "each problem needs its own operators and sigma buffer");
+      v.push_back(ops[i]->p.get());
     }
+    if (!ctx->batch || !ctx->batch->matches(v, precision)) {
+      ctx->batch.reset();
+      ctx->batch = dmrg::build_batch(v, precision, ctx->stream);
+    }
+    dmrg::BatchPlan& B = *ctx->batch;
+    if (!B.tuned && !(flags & DMRG_BATCH_NO_TUNE)) {
+      B.bind(psi, sigma, ctx->stream);
+      B.autotune(ctx->stream);
+    }
+    B.run(psi, sigma, !(flags & DMRG_BATCH_EAGER), ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_default, double* ms_tuned) {
+  if (!ctx || !ops) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    dmrg::sigma_autotune(*ops->p, precision, ctx->stream);
+    if (ms_default) *ms_default = ops->p->tune_ms_default[precision];
+    if (ms_tuned) *ms_tuned = ops->p->tune_ms_best[precision];
     return (int)DMRG_OK;
   });
 }

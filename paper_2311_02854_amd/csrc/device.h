@@ -40,6 +40,13 @@ struct XcdMap {
 };
 
 enum : int32_t { GF_TRANS_A = 1, GF_TRANS_B = 2, GF_IDENT_A = 4 };
+// GTask::accumulate bits: add to the existing C; C is binary64 whatever the
+// operand precision (the sigma output; buffer 1 always is)
+enum : int32_t { GT_ACCUM = 1, GT_C64 = 2 };
+// Workgroup tile shapes of the grouped GEMM (rows x columns of C)
+enum : int { TILE_64x64 = 0, TILE_32x32 = 1, TILE_64x32 = 2, TILE_32x64 = 3, NTILE = 4 };
+inline int tile_rows(int t) { return (t == TILE_32x32 || t == TILE_32x64) ? 32 : 64; }
+inline int tile_cols(int t) { return (t == TILE_32x32 || t == TILE_64x32) ? 32 : 64; }
 
 struct GContrib {
   int32_t K;
@@ -69,14 +76,27 @@ void ev_destroy(void* ev);
 void ev_record(void* ev, void* stream);
 float ev_elapsed_ms(void* a, void* b);   // both recorded and complete
 
+// streams and graphs: a non-blocking stream of default priority, stream
+// capture (thread-local mode) into an executable graph, and its launch
+void* stream_create();
+void stream_destroy(void* s);
+void graph_begin(void* s);
+void* graph_end(void* s);                 // returns the executable graph
+void graph_launch(void* exec, void* stream);
+void graph_destroy(void* exec);
+
 // --- kernels (all asynchronous on `stream`) --------------------------------
 // Grouped, batched GEMM over a task list (tasks/contribs in device memory).
-// elem: P_F64 (all buffers double) or P_F32 (all buffers float, FP32 MFMA)
-// or P_BF16X3 (float buffers, split-bf16 MFMA, FP32 accumulation).
+// elem: P_F64 (all buffers double) or P_F32 (operand buffers float, FP32 MFMA)
+// or P_BF16X3 (float operand buffers, split-bf16 MFMA, FP32 accumulation);
+// outputs of tasks flagged GT_C64 are double in every mode.  tile: TILE_*,
+// the shape the tasks' tiles_m / tiles_n were counted with.  grid_per_xcd > 0
+// caps the workgroups per XCD (persistent launch), else one per job.
 // bucket_dev[bucket_begin[x] + b] is the task of XCD x holding its job b << shift
 // (clamped to the XCD's last task); it bounds the kernel's job -> task search.
 void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
-                 const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, void* stream);
+                 const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, int tile,
+                 int64_t grid_per_xcd, void* stream);
 
 void k_fill(double* x, double v, int64_t n, void* stream);
 void k_fill_f(float* x, float v, int64_t n, void* stream);

@@ -51,13 +51,17 @@ class DevTable {
   bool dirty_ = true;
 };
 
-// A list of GEMM tasks executed by one gemm_launch.
+// A list of GEMM tasks executed by one gemm_launch.  The host list is tile
+// independent; upload(tile) counts the tasks' tiles for one workgroup tile
+// shape, splits them into pieces and assigns the pieces to XCDs.  One device
+// copy per tile shape can be kept (they share the contribution array).
 class GemmList {
  public:
-  static constexpr int TILE = 64;
+  int tile = TILE_64x64;       // shape used by run()
+  int64_t grid_per_xcd = 0;    // > 0: persistent launch with this many workgroups per XCD
   std::vector<GTask> tasks;
   std::vector<GContrib> contribs;
-  int64_t njobs = 0;
+  int64_t njobs = 0;           // jobs at 64x64 tiles (for reporting)
   double flops = 0;
   int64_t ngemm = 0;
 
@@ -69,19 +73,20 @@ class GemmList {
   GemmList& operator=(GemmList&& o) noexcept {
     if (this != &o) {
       release();
+      tile = o.tile;
+      grid_per_xcd = o.grid_per_xcd;
       tasks = std::move(o.tasks);
       contribs = std::move(o.contribs);
       njobs = o.njobs;
       flops = o.flops;
       ngemm = o.ngemm;
-      dtasks_ = o.dtasks_;
       dcontribs_ = o.dcontribs_;
-      dbucket_ = o.dbucket_;
-      map_ = o.map_;
-      ntasks_dev_ = o.ntasks_dev_;
-      o.dtasks_ = nullptr;
       o.dcontribs_ = nullptr;
-      o.dbucket_ = nullptr;
+      ncontribs_dev_ = o.ncontribs_dev_;
+      for (int t = 0; t < NTILE; ++t) {
+        dev_[t] = o.dev_[t];
+        o.dev_[t] = Dev{};
+      }
     }
     return *this;
   }
@@ -91,11 +96,11 @@ class GemmList {
     t.M = M;
     t.N = N;
     t.nbatch = nbatch;
-    t.tiles_m = (M + TILE - 1) / TILE;
-    t.tiles_n = (N + TILE - 1) / TILE;
+    t.tiles_m = (M + 63) / 64;
+    t.tiles_n = (N + 63) / 64;
     t.c_buf = c_buf;
     t.ldc = ldc;
-    t.accumulate = accumulate ? 1 : 0;
+    t.accumulate = (accumulate ? GT_ACCUM : 0) | (c_buf == 1 ? GT_C64 : 0);
     t.c_off = c_off;
     t.c_bstride = c_bstride;
     t.contrib_begin = t.contrib_end = (int32_t)contribs.size();
@@ -114,7 +119,7 @@ class GemmList {
   void end() {
     GTask& t = tasks.back();
     if (t.M <= 0 || t.N <= 0 || t.nbatch <= 0 ||
-        (t.contrib_begin == t.contrib_end && t.accumulate)) {
+        (t.contrib_begin == t.contrib_end && (t.accumulate & GT_ACCUM))) {
       contribs.resize(t.contrib_begin);
       tasks.pop_back();
       return;
@@ -122,21 +127,27 @@ class GemmList {
     t.job_begin = njobs;
     njobs += (int64_t)t.tiles_m * t.tiles_n * t.nbatch;
   }
-  bool empty() const { return tasks.empty() && ntasks_dev_ == 0; }
+  bool empty() const { return tasks.empty() && ncontribs_dev_ == 0 && !any_dev(); }
 
-  // Estimated MFMA work of one job of task t (k steps x active 16x16 sub-tiles).
-  double job_cost(const GTask& t) const {
-    const int am = t.M < TILE ? t.M : TILE, an = t.N < TILE ? t.N : TILE;
+  // Estimated MFMA work of one job of task t at tile shape `tl` (k steps x
+  // active 16x16 sub-tiles of the workgroup).
+  static double job_cost(const GTask& t, const GContrib* cs, int tl) {
+    const int tr = tile_rows(tl), tc = tile_cols(tl);
+    const int am = t.M < tr ? t.M : tr, an = t.N < tc ? t.N : tc;
     const double sub = double((am + 15) / 16) * ((an + 15) / 16);
     double c = 64.0;
     for (int i = t.contrib_begin; i < t.contrib_end; ++i) {
-      const GContrib& g = contribs[i];
+      const GContrib& g = cs[i];
       c += (g.flags & GF_IDENT_A) ? 4.0 : g.nred * (((g.K + 3) / 4) * sub + 16.0);
     }
     return c;
   }
+  static int64_t jobs_at(const GTask& t, int tl) {
+    return (int64_t)((t.M + tile_rows(tl) - 1) / tile_rows(tl)) * ((t.N + tile_cols(tl) - 1) / tile_cols(tl)) *
+           t.nbatch;
+  }
 
-  // Concatenate host-side lists, ordering tasks by decreasing job cost so the
+  // Concatenate host lists, ordering tasks by decreasing job cost so the
   // longest jobs are dispatched first.  Contribution order inside a task is
   // kept, so results do not depend on the ordering.
   static GemmList merge_by_cost(const std::vector<GemmList*>& parts) {
@@ -148,7 +159,8 @@ class GemmList {
     std::vector<Ref> refs;
     GemmList m;
     for (const GemmList* p : parts) {
-      for (int t = 0; t < (int)p->tasks.size(); ++t) refs.push_back({p, t, p->job_cost(p->tasks[t])});
+      for (int t = 0; t < (int)p->tasks.size(); ++t)
+        refs.push_back({p, t, job_cost(p->tasks[t], p->contribs.data(), TILE_64x64)});
       m.flops += p->flops;
       m.ngemm += p->ngemm;
     }
@@ -166,114 +178,145 @@ class GemmList {
     }
     return m;
   }
-  // Split tasks into job-range pieces, assign them to XCDs (longest
-  // processing time first) and upload the per-XCD task lists.
-  void upload() {
-    release();
-    std::vector<GTask> dev;
-    std::memset(&map_, 0, sizeof(map_));
-    if (!tasks.empty()) {
-      std::vector<double> cj(tasks.size());
-      double total = 0;
-      for (size_t t = 0; t < tasks.size(); ++t) {
-        cj[t] = job_cost(tasks[t]);
-        total += cj[t] * jobs_of(tasks[t]);
-      }
-      const double piece_cost = std::max(total / (NXCD * 32.0), 1.0);
-      struct Piece {
-        size_t t;
-        int64_t off, n;
-        double c;
-      };
-      std::vector<Piece> pcs;
-      for (size_t t = 0; t < tasks.size(); ++t) {
-        const int64_t nj = jobs_of(tasks[t]);
-        int64_t np = (int64_t)std::ceil(cj[t] * nj / piece_cost);
-        np = std::max<int64_t>(1, std::min<int64_t>(np, nj));
-        for (int64_t i = 0; i < np; ++i) {
-          const int64_t a = nj * i / np, b = nj * (i + 1) / np;
-          if (b > a) pcs.push_back({t, a, b - a, cj[t]});
-        }
-      }
-      std::stable_sort(pcs.begin(), pcs.end(), [](const Piece& a, const Piece& b) {
-        return a.c * a.n > b.c * b.n;
-      });
-      std::vector<std::vector<Piece>> per(NXCD);
-      double load[NXCD] = {0};
-      for (const Piece& p : pcs) {
-        int x = 0;
-        for (int i = 1; i < NXCD; ++i)
-          if (load[i] < load[x]) x = i;
-        load[x] += p.c * p.n;
-        per[x].push_back(p);
-      }
-      for (int x = 0; x < NXCD; ++x) {
-        // longest jobs first inside an XCD
-        std::stable_sort(per[x].begin(), per[x].end(), [](const Piece& a, const Piece& b) { return a.c > b.c; });
-        map_.task_begin[x] = (int)dev.size();
-        int64_t jb = 0;
-        for (const Piece& p : per[x]) {
-          GTask g = tasks[p.t];
-          g.job_begin = jb;
-          g.job_off = p.off;
-          g.njob = p.n;
-          jb += p.n;
-          dev.push_back(g);
-        }
-        map_.njobs[x] = jb;
-        map_.max_jobs = std::max(map_.max_jobs, jb);
-      }
-      map_.task_begin[NXCD] = (int)dev.size();
-      map_.shift = 0;
-      while ((map_.max_jobs >> map_.shift) > (int64_t(1) << 14)) ++map_.shift;
-      std::vector<int> bucket;
-      for (int x = 0; x < NXCD; ++x) {
-        map_.bucket_begin[x] = (int)bucket.size();
-        const int tb = map_.task_begin[x], te = map_.task_begin[x + 1];
-        const int64_t nb = (map_.njobs[x] >> map_.shift) + 1;
-        int ti = tb;
-        for (int64_t b = 0; b <= nb; ++b) {
-          const int64_t job = b << map_.shift;
-          while (ti + 1 < te && dev[ti + 1].job_begin <= job) ++ti;
-          bucket.push_back(te > tb ? ti : tb);
-        }
-      }
-      map_.bucket_begin[NXCD] = (int)bucket.size();
-      dbucket_ = (int*)dev_alloc(std::max<size_t>(1, bucket.size()) * sizeof(int));
-      dev_h2d(dbucket_, bucket.data(), bucket.size() * sizeof(int));
+
+  // Count tiles for shape tl, split tasks into job-range pieces, assign them
+  // to XCDs (longest processing time first) and upload the per-XCD lists.
+  void upload(int tl) {
+    DMRG_CHECK(tl >= 0 && tl < NTILE, DMRG_EINVAL, "unknown tile shape");
+    free_dev(dev_[tl]);
+    if (tasks.empty()) return;
+    if (!dcontribs_) {
+      dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
+      if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
+      ncontribs_dev_ = contribs.size();
     }
-    ntasks_dev_ = (int)dev.size();
-    if (dev.empty()) return;
-    dtasks_ = (GTask*)dev_alloc(dev.size() * sizeof(GTask));
-    dev_h2d(dtasks_, dev.data(), dev.size() * sizeof(GTask));
-    dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
-    if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
+    Dev& D = dev_[tl];
+    std::memset(&D.map, 0, sizeof(D.map));
+    std::vector<GTask> dev;
+    std::vector<double> cj(tasks.size());
+    std::vector<int64_t> nj(tasks.size());
+    double total = 0;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+      cj[t] = job_cost(tasks[t], contribs.data(), tl);
+      nj[t] = jobs_at(tasks[t], tl);
+      total += cj[t] * nj[t];
+    }
+    const double piece_cost = std::max(total / (NXCD * 32.0), 1.0);
+    struct Piece {
+      size_t t;
+      int64_t off, n;
+      double c;
+    };
+    std::vector<Piece> pcs;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+      int64_t np = (int64_t)std::ceil(cj[t] * nj[t] / piece_cost);
+      np = std::max<int64_t>(1, std::min<int64_t>(np, nj[t]));
+      for (int64_t i = 0; i < np; ++i) {
+        const int64_t a = nj[t] * i / np, b = nj[t] * (i + 1) / np;
+        if (b > a) pcs.push_back({t, a, b - a, cj[t]});
+      }
+    }
+    std::stable_sort(pcs.begin(), pcs.end(), [](const Piece& a, const Piece& b) { return a.c * a.n > b.c * b.n; });
+    std::vector<std::vector<Piece>> per(NXCD);
+    double load[NXCD] = {0};
+    for (const Piece& p : pcs) {
+      int x = 0;
+      for (int i = 1; i < NXCD; ++i)
+        if (load[i] < load[x]) x = i;
+      load[x] += p.c * p.n;
+      per[x].push_back(p);
+    }
+    for (int x = 0; x < NXCD; ++x) {
+      // longest jobs first inside an XCD
+      std::stable_sort(per[x].begin(), per[x].end(), [](const Piece& a, const Piece& b) { return a.c > b.c; });
+      D.map.task_begin[x] = (int)dev.size();
+      int64_t jb = 0;
+      for (const Piece& p : per[x]) {
+        GTask g = tasks[p.t];
+        g.tiles_m = (g.M + tile_rows(tl) - 1) / tile_rows(tl);
+        g.tiles_n = (g.N + tile_cols(tl) - 1) / tile_cols(tl);
+        g.job_begin = jb;
+        g.job_off = p.off;
+        g.njob = p.n;
+        jb += p.n;
+        dev.push_back(g);
+      }
+      D.map.njobs[x] = jb;
+      D.map.max_jobs = std::max(D.map.max_jobs, jb);
+    }
+    D.map.task_begin[NXCD] = (int)dev.size();
+    D.map.shift = 0;
+    while ((D.map.max_jobs >> D.map.shift) > (int64_t(1) << 14)) ++D.map.shift;
+    std::vector<int> bucket;
+    for (int x = 0; x < NXCD; ++x) {
+      D.map.bucket_begin[x] = (int)bucket.size();
+      const int tb = D.map.task_begin[x], te = D.map.task_begin[x + 1];
+      const int64_t nb = (D.map.njobs[x] >> D.map.shift) + 1;
+      int ti = tb;
+      for (int64_t b = 0; b <= nb; ++b) {
+        const int64_t job = b << D.map.shift;
+        while (ti + 1 < te && dev[ti + 1].job_begin <= job) ++ti;
+        bucket.push_back(te > tb ? ti : tb);
+      }
+    }
+    D.map.bucket_begin[NXCD] = (int)bucket.size();
+    D.bucket = (int*)dev_alloc(std::max<size_t>(1, bucket.size()) * sizeof(int));
+    dev_h2d(D.bucket, bucket.data(), bucket.size() * sizeof(int));
+    D.tasks = (GTask*)dev_alloc(dev.size() * sizeof(GTask));
+    dev_h2d(D.tasks, dev.data(), dev.size() * sizeof(GTask));
+    D.ntasks = (int)dev.size();
   }
-  static int64_t jobs_of(const GTask& t) { return (int64_t)t.tiles_m * t.tiles_n * t.nbatch; }
-  void run(DevTable& tab, const void* p0, void* p1, int elem, void* stream) {
-    if (!dtasks_) upload();
-    if (ntasks_dev_ == 0) return;
-    gemm_launch(dtasks_, ntasks_dev_, map_, dcontribs_, dbucket_, tab.device(), p0, p1, elem, stream);
+  void upload() { upload(tile); }
+  bool uploaded(int tl) const { return dev_[tl].tasks != nullptr || tasks.empty(); }
+  void run(DevTable& tab, const void* p0, void* p1, int elem, void* stream) { run_tile(tile, tab, p0, p1, elem, stream); }
+  void run_tile(int tl, DevTable& tab, const void* p0, void* p1, int elem, void* stream) {
+    if (!dev_[tl].tasks) upload(tl);
+    const Dev& D = dev_[tl];
+    if (D.ntasks == 0) return;
+    gemm_launch(D.tasks, D.ntasks, D.map, dcontribs_, D.bucket, tab.device(), p0, p1, elem, tl, grid_per_xcd,
+                stream);
   }
   void release() {
-    dev_free(dtasks_);
+    for (int t = 0; t < NTILE; ++t) free_dev(dev_[t]);
     dev_free(dcontribs_);
-    dev_free(dbucket_);
-    dtasks_ = nullptr;
     dcontribs_ = nullptr;
-    dbucket_ = nullptr;
+    ncontribs_dev_ = 0;
+  }
+  // drop the device copy of one tile shape (rebuilt on demand from the host list)
+  void release_tile(int t) {
+    if (!tasks.empty()) free_dev(dev_[t]);
   }
   void clear_host() {
     std::vector<GTask>().swap(tasks);
     std::vector<GContrib>().swap(contribs);
   }
+  size_t host_bytes() const { return tasks.size() * sizeof(GTask) + contribs.size() * sizeof(GContrib); }
+  size_t device_bytes() const {
+    size_t b = ncontribs_dev_ * sizeof(GContrib);
+    for (int t = 0; t < NTILE; ++t) b += (size_t)dev_[t].ntasks * sizeof(GTask);
+    return b;
+  }
 
  private:
-  GTask* dtasks_ = nullptr;
+  struct Dev {
+    GTask* tasks = nullptr;
+    int* bucket = nullptr;
+    XcdMap map{};
+    int ntasks = 0;
+  };
+  static void free_dev(Dev& d) {
+    dev_free(d.tasks);
+    dev_free(d.bucket);
+    d = Dev{};
+  }
+  bool any_dev() const {
+    for (int t = 0; t < NTILE; ++t)
+      if (dev_[t].ntasks) return true;
+    return false;
+  }
   GContrib* dcontribs_ = nullptr;
-  int* dbucket_ = nullptr;
-  XcdMap map_{};
-  int ntasks_dev_ = 0;
+  size_t ncontribs_dev_ = 0;
+  Dev dev_[NTILE];
 };
 
 inline GContrib make_contrib(int K, int flags, int a_buf, int64_t a_off, int lda, int b_buf, int64_t b_off,

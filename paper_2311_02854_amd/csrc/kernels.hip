@@ -80,6 +80,29 @@ float ev_elapsed_ms(void* a, void* b) {
   return ms;
 }
 
+void* stream_create() {
+  hipStream_t s;
+  HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  return (void*)s;
+}
+void stream_destroy(void* s) {
+  if (s) (void)hipStreamDestroy(S(s));
+}
+void graph_begin(void* s) { HIPCHK(hipStreamBeginCapture(S(s), hipStreamCaptureModeThreadLocal)); }
+void* graph_end(void* s) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamEndCapture(S(s), &g));
+  hipGraphExec_t e = nullptr;
+  hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (r != hipSuccess) throw Error(DMRG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(r));
+  return (void*)e;
+}
+void graph_launch(void* exec, void* stream) { HIPCHK(hipGraphLaunch((hipGraphExec_t)exec, S(stream))); }
+void graph_destroy(void* exec) {
+  if (exec) (void)hipGraphExecDestroy((hipGraphExec_t)exec);
+}
+
 double wall_seconds() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -90,7 +113,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, BK = 32, NT = 256;
+constexpr int BK = 32, NT = 256;
 
 // Operand precision policies.  FP64 and FP32 stage op(A) and op(B) tiles in
 // LDS k-major ([k][row], rows contiguous) and feed 16x16x4 MFMAs one element
@@ -120,15 +143,17 @@ struct PolBF3 {
   static constexpr int RL = 4, RV = 1;
 };
 
-template <class P, bool S = P::split>
+// Tile shape: the four waves form a 2 x 2 grid, each wave owns WM x WN
+// sub-tiles of 16 x 16, so the workgroup tile is (32 WM) x (32 WN).
+template <class P, int BM_, int BN_, bool S = P::split>
 struct alignas(16) Smem {
-  typename P::T A[BK][BM + P::PAD];
-  typename P::T B[BK][BN + P::PAD];
+  typename P::T A[BK][BM_ + P::PAD];
+  typename P::T B[BK][BN_ + P::PAD];
 };
-template <class P>
-struct alignas(16) Smem<P, true> {
-  uint16_t Ah[BM][BK + P::PAD], Al[BM][BK + P::PAD];
-  uint16_t Bh[BN][BK + P::PAD], Bl[BN][BK + P::PAD];
+template <class P, int BM_, int BN_>
+struct alignas(16) Smem<P, BM_, BN_, true> {
+  uint16_t Ah[BM_][BK + P::PAD], Al[BM_][BK + P::PAD];
+  uint16_t Bh[BN_][BK + P::PAD], Bl[BN_][BK + P::PAD];
 };
 
 __device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c) {
@@ -165,10 +190,10 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
   return lo;
 }
 
-// Per-thread view of one 64 x BK operand tile: element (r, k) of op(X) sits
+// Per-thread view of one ROWS x BK operand tile: element (r, k) of op(X) sits
 // at X + r*sr + k*sk.  When k is contiguous (sk == 1) threads walk k fastest
-// (32 per row, 8 rows per pass), otherwise r fastest (64 per row, 4 k per
-// pass); either way every thread owns 8 elements.
+// (32 per row, 8 rows per pass), otherwise r fastest (ROWS per row, 256/ROWS
+// k per pass); either way every thread owns E = ROWS*BK/256 elements.
 template <typename T>
 struct Opnd {
   const T* origin;   // element (0, 0) of op(X): always a valid address
@@ -181,7 +206,7 @@ struct Opnd {
   T scale;
 };
 
-template <typename T>
+template <int ROWS, typename T>
 __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, int64_t sk, int r0, int rows,
                                            int K, T scale) {
   const int tid = threadIdx.x;
@@ -192,11 +217,11 @@ __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, i
     o.k_inc = 0;
     o.step_it = 8 * sr;
   } else {
-    o.r_first = tid & 63;
-    o.k_first = tid >> 6;
+    o.r_first = tid % ROWS;
+    o.k_first = tid / ROWS;
     o.r_inc = 0;
-    o.k_inc = 4;
-    o.step_it = 4 * sk;
+    o.k_inc = NT / ROWS;
+    o.step_it = (NT / ROWS) * sk;
   }
   o.origin = X;
   o.base = X + (int64_t)(r0 + o.r_first) * sr + (int64_t)o.k_first * sk;
@@ -207,32 +232,31 @@ __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, i
 }
 
 // Out-of-range elements load from the operand's origin (always valid) and
-// are zeroed by a select, so the eight loads issue back to back without
-// branches; nothing consumes them until the next LDS store.
-template <typename T>
-__device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[8], bool (&ok)[8]) {
+// are zeroed by a select, so the loads issue back to back without branches;
+// nothing consumes them until the next LDS store.
+template <int E, typename T>
+__device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E], bool (&ok)[E]) {
   const T* p = o.base + (int64_t)(k0 / BK) * o.step_k;
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
+  for (int it = 0; it < E; ++it) {
     const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
     ok[it] = (r < o.rows) & (k < o.K);
     v[it] = *(ok[it] ? p + it * o.step_it : o.origin);
   }
 }
 
-template <typename T, int LD>
-__device__ __forceinline__ void opnd_store(const Opnd<T>& o, const T (&v)[8], const bool (&ok)[8],
-                                           T (*L)[LD]) {
+template <int E, typename T, int LD>
+__device__ __forceinline__ void opnd_store(const Opnd<T>& o, const T (&v)[E], const bool (&ok)[E], T (*L)[LD]) {
 #pragma unroll
-  for (int it = 0; it < 8; ++it)
+  for (int it = 0; it < E; ++it)
     L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = ok[it] ? v[it] * o.scale : T(0);
 }
 
-template <int LD>
-__device__ __forceinline__ void opnd_store_split(const Opnd<float>& o, const float (&v)[8], const bool (&ok)[8],
+template <int E, int LD>
+__device__ __forceinline__ void opnd_store_split(const Opnd<float>& o, const float (&v)[E], const bool (&ok)[E],
                                                  uint16_t (*H)[LD], uint16_t (*Lo)[LD]) {
 #pragma unroll
-  for (int it = 0; it < 8; ++it) {
+  for (int it = 0; it < E; ++it) {
     const float x = ok[it] ? v[it] * o.scale : 0.0f;
     const uint16_t h = bf16_rne(x);
     const uint16_t l = bf16_rne(x - __uint_as_float((uint32_t)h << 16));
@@ -249,8 +273,8 @@ struct Step {
 };
 
 // Grouped GEMM over a task list (see device.h).  Operand buffers hold P::T;
-// the output is P::T except buffer 1 (p1), which is always binary64.
-template <class P>
+// the output is P::T, or binary64 for tasks flagged GT_C64 (buffer 1 is p1).
+template <class P, int WM, int WN>
 __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ tasks, const XcdMap map,
                                                   const GContrib* __restrict__ contribs,
                                                   const int* __restrict__ bucket_all,
@@ -258,9 +282,10 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
                                                   const typename P::T* p0, double* p1) {
   using T = typename P::T;
   using Acc = typename P::Acc;
-  __shared__ Smem<P> sm;
+  constexpr int BM = 32 * WM, BN = 32 * WN, EA = BM * BK / NT, EB = BN * BK / NT;
+  __shared__ Smem<P, BM, BN> sm;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
   const int lr = lane & 15, lk = lane >> 4;
   const int xcd = blockIdx.x % NXCD;
   const int64_t njobs = map.njobs[xcd];
@@ -274,13 +299,23 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
     const int tile = (int)(local - batch * tiles);
     const int m0 = (tile / Tk.tiles_n) * BM, n0 = (tile % Tk.tiles_n) * BN;
     const int mrem = Tk.M - m0 - wm, nrem = Tk.N - n0 - wn;
-    const bool act00 = mrem > 0 && nrem > 0, act01 = mrem > 0 && nrem > 16;
-    const bool act10 = mrem > 16 && nrem > 0, act11 = mrem > 16 && nrem > 16;
-    Acc acc[2][2];
+    // sub-tile (i, j) of this wave holds valid rows and columns
+    bool act[WM][WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+      for (int j = 0; j < WN; ++j) act[i][j] = mrem > 16 * i && nrem > 16 * j;
+    const bool any = act[0][0];
+    bool full = true;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) full = full && act[i][j];
+    Acc acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
     // identity contributions: acc += alpha op(B)  (M == K)
     for (int ci = Tk.contrib_begin; ci < Tk.contrib_end; ++ci) {
@@ -292,9 +327,9 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
         T alpha = (T)Cb.alpha;
         if (Cb.s_buf >= 0) alpha *= opp(Cb.s_buf)[Cb.s_off + batch * Cb.s_bstride + (int64_t)t * Cb.s_rstride];
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < 2; ++ni)
+          for (int ni = 0; ni < WN; ++ni)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
@@ -318,16 +353,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
       if (Cb.s_buf >= 0) alpha *= opp(Cb.s_buf)[Cb.s_off + batch * Cb.s_bstride + (int64_t)s.t * Cb.s_rstride];
       const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
       // op(A)(m, k): stored M x K (lda) or K x M;  op(B)(k, n) seen as (n, k)
-      opnd_setup<T>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
-      opnd_setup<T>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
+      opnd_setup<BM>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
+      opnd_setup<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
     };
     Step cur{first_from(Tk.contrib_begin), 0, 0, 0};
     if (cur.ci < Tk.contrib_end) {
       Opnd<T> oa, ob;
       cur.K = contribs[cur.ci].K;
       setup(cur, oa, ob);
-      T ra[8], rb[8];
-      bool ka[8], kb[8];
+      T ra[EA], rb[EB];
+      bool ka[EA], kb[EB];
       opnd_load(oa, 0, ra, ka);
       opnd_load(ob, 0, rb, kb);
       for (;;) {
@@ -362,58 +397,63 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
         }
         if constexpr (P::split) {
           // one 16x16x32 step covers the whole k tile (entries past K are 0)
-          if (act00) {
-            bf8_t ah[2], al[2], bh[2], bl[2];
+          if (any) {
+            bf8_t ah[WM], al[WM], bh[WN], bl[WN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < WM; ++i) {
               ah[i] = *reinterpret_cast<const bf8_t*>(&sm.Ah[wm + i * 16 + lr][8 * lk]);
               al[i] = *reinterpret_cast<const bf8_t*>(&sm.Al[wm + i * 16 + lr][8 * lk]);
-              bh[i] = *reinterpret_cast<const bf8_t*>(&sm.Bh[wn + i * 16 + lr][8 * lk]);
-              bl[i] = *reinterpret_cast<const bf8_t*>(&sm.Bl[wn + i * 16 + lr][8 * lk]);
             }
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
+            for (int j = 0; j < WN; ++j) {
+              bh[j] = *reinterpret_cast<const bf8_t*>(&sm.Bh[wn + j * 16 + lr][8 * lk]);
+              bl[j] = *reinterpret_cast<const bf8_t*>(&sm.Bl[wn + j * 16 + lr][8 * lk]);
+            }
 #pragma unroll
-              for (int ni = 0; ni < 2; ++ni) {
-                const bool on = (mi ? act10 : act00) && (ni ? (mi ? act11 : act01) : true);
-                if (on) {
+            for (int mi = 0; mi < WM; ++mi)
+#pragma unroll
+              for (int ni = 0; ni < WN; ++ni)
+                if (act[mi][ni]) {
                   acc[mi][ni] = mfma32(al[mi], bh[ni], acc[mi][ni]);
                   acc[mi][ni] = mfma32(ah[mi], bl[ni], acc[mi][ni]);
                   acc[mi][ni] = mfma32(ah[mi], bh[ni], acc[mi][ni]);
                 }
-              }
           }
-        } else if (act11 && kend == BK) {
+        } else if (full && kend == BK) {
           // full tile: unrolled; the fragments of step kk+4 are read from
           // LDS while the MFMAs of step kk run
-          T fa[2][2], fb[2][2];
-          fa[0][0] = sm.A[lk][wm + lr];
-          fa[0][1] = sm.A[lk][wm + 16 + lr];
-          fb[0][0] = sm.B[lk][wn + lr];
-          fb[0][1] = sm.B[lk][wn + 16 + lr];
+          T fa[2][WM], fb[2][WN];
+#pragma unroll
+          for (int i = 0; i < WM; ++i) fa[0][i] = sm.A[lk][wm + i * 16 + lr];
+#pragma unroll
+          for (int j = 0; j < WN; ++j) fb[0][j] = sm.B[lk][wn + j * 16 + lr];
 #pragma unroll
           for (int s = 0; s < BK / 4; ++s) {
             const int cb = s & 1, nb = cb ^ 1;
             if (s + 1 < BK / 4) {
               const int kn = 4 * (s + 1) + lk;
-              fa[nb][0] = sm.A[kn][wm + lr];
-              fa[nb][1] = sm.A[kn][wm + 16 + lr];
-              fb[nb][0] = sm.B[kn][wn + lr];
-              fb[nb][1] = sm.B[kn][wn + 16 + lr];
+#pragma unroll
+              for (int i = 0; i < WM; ++i) fa[nb][i] = sm.A[kn][wm + i * 16 + lr];
+#pragma unroll
+              for (int j = 0; j < WN; ++j) fb[nb][j] = sm.B[kn][wn + j * 16 + lr];
             }
-            acc[0][0] = mfma4(fa[cb][0], fb[cb][0], acc[0][0]);
-            acc[0][1] = mfma4(fa[cb][0], fb[cb][1], acc[0][1]);
-            acc[1][0] = mfma4(fa[cb][1], fb[cb][0], acc[1][0]);
-            acc[1][1] = mfma4(fa[cb][1], fb[cb][1], acc[1][1]);
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+              for (int j = 0; j < WN; ++j) acc[i][j] = mfma4(fa[cb][i], fb[cb][j], acc[i][j]);
           }
-        } else if (act00) {
+        } else if (any) {
           for (int kk = 0; kk < kend; kk += 4) {
-            T a0 = sm.A[kk + lk][wm + lr], a1 = sm.A[kk + lk][wm + 16 + lr];
-            T b0 = sm.B[kk + lk][wn + lr], b1 = sm.B[kk + lk][wn + 16 + lr];
-            acc[0][0] = mfma4(a0, b0, acc[0][0]);
-            if (act01) acc[0][1] = mfma4(a0, b1, acc[0][1]);
-            if (act10) acc[1][0] = mfma4(a1, b0, acc[1][0]);
-            if (act11) acc[1][1] = mfma4(a1, b1, acc[1][1]);
+            T fa[WM], fb[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i) fa[i] = sm.A[kk + lk][wm + i * 16 + lr];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) fb[j] = sm.B[kk + lk][wn + j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+              for (int j = 0; j < WN; ++j)
+                if (act[i][j]) acc[i][j] = mfma4(fa[i], fb[j], acc[i][j]);
           }
         }
         __syncthreads();
@@ -424,41 +464,65 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
     // result element v of lane l in sub-tile (mi, ni): row RL*(l/16) + RV*v, column l%16
     auto store = [&](auto* Cp) {
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < WN; ++ni)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
             if (r < Tk.M && c < Tk.N) {
               auto* dst = Cp + (int64_t)r * Tk.ldc + c;
               auto val = (decltype(*dst + 0))acc[mi][ni][v];
-              if (Tk.accumulate) val += *dst;
+              if (Tk.accumulate & GT_ACCUM) val += *dst;
               *dst = val;
             }
           }
     };
-    if (Tk.c_buf == 1)
-      store(p1 + Tk.c_off + batch * Tk.c_bstride);
+    if (Tk.accumulate & GT_C64)
+      store((Tk.c_buf == 1 ? p1 : reinterpret_cast<double*>(table[Tk.c_buf])) + Tk.c_off + batch * Tk.c_bstride);
     else
       store(table[Tk.c_buf] + Tk.c_off + batch * Tk.c_bstride);
   }
 }
 
+template <class P>
+static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, const XcdMap& map,
+                           const GContrib* c, const int* bk, typename P::T* const* tab, const typename P::T* p0,
+                           double* p1) {
+  switch (tile) {
+    case TILE_64x64:
+      hipLaunchKernelGGL((gemm_kernel<P, 2, 2>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      break;
+    case TILE_32x32:
+      hipLaunchKernelGGL((gemm_kernel<P, 1, 1>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      break;
+    case TILE_64x32:
+      hipLaunchKernelGGL((gemm_kernel<P, 2, 1>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      break;
+    case TILE_32x64:
+      hipLaunchKernelGGL((gemm_kernel<P, 1, 2>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      break;
+    default:
+      throw Error(DMRG_EINVAL, "unknown GEMM tile shape");
+  }
+}
+
 void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
-                 const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
+                 const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, int tile,
+                 int64_t grid_per_xcd, void* stream) {
   if (ntasks == 0 || map.max_jobs == 0) return;
-  const int64_t per = map.max_jobs < (1 << 19) ? map.max_jobs : (1 << 19);
-  const dim3 grid((unsigned)(per * NXCD)), block(NT);
+  int64_t per = map.max_jobs < (1 << 19) ? map.max_jobs : (1 << 19);
+  if (grid_per_xcd > 0 && grid_per_xcd < per) per = grid_per_xcd;
+  const dim3 grid((unsigned)(per * NXCD));
   if (elem == P_F64) {
-    hipLaunchKernelGGL(gemm_kernel<PolF64>, grid, block, 0, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
-                       (double* const*)table_dev, (const double*)p0, (double*)p1);
+    launch_variant<PolF64>(tile, grid, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+                           (double* const*)table_dev, (const double*)p0, (double*)p1);
   } else if (elem == P_F32) {
-    hipLaunchKernelGGL(gemm_kernel<PolF32>, grid, block, 0, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
-                       (float* const*)table_dev, (const float*)p0, (double*)p1);
+    launch_variant<PolF32>(tile, grid, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+                           (float* const*)table_dev, (const float*)p0, (double*)p1);
   } else if (elem == P_BF16X3) {
-    hipLaunchKernelGGL(gemm_kernel<PolBF3>, grid, block, 0, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
-                       (float* const*)table_dev, (const float*)p0, (double*)p1);
+    launch_variant<PolBF3>(tile, grid, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+                           (float* const*)table_dev, (const float*)p0, (double*)p1);
   } else {
     throw Error(DMRG_EINVAL, "unknown GEMM precision");
   }

@@ -20,6 +20,7 @@
 #include "ops.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <set>
@@ -160,6 +161,8 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
   DMRG_CHECK(Na >= 0 && Nb >= 0 && Na <= K && Nb <= K, DMRG_EINVAL, "electron numbers out of range");
   auto ops = std::make_unique<Ops>();
   Ops& O = *ops;
+  static std::atomic<uint64_t> serial_counter{0};
+  O.serial = ++serial_counter;
   O.K = K;
   O.Na = Na;
   O.Nb = Nb;
@@ -824,8 +827,7 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
         DMRG_CHECK(c.b_buf != 1 && ((c.flags & GF_IDENT_A) || c.a_buf != 1), DMRG_EINTERNAL,
                    "sigma plan reads its output buffer");
       }
-      m.upload();
-      m.clear_host();
+      m.upload(TILE_64x64);
       O.launches.push_back(std::move(m));
     }
     O.sigma_bufs.assign(bufs.begin(), bufs.end());
@@ -852,20 +854,106 @@ void sigma_run(Ops& O, const double* psi, double* sigma, int prec, void* stream)
     tab = O.tab32.get();
     p0 = O.psi32;
   }
+  const bool tuned = O.tile_choice[prec].size() == O.launches.size();
+  auto launch = [&](size_t i) {
+    GemmList& l = O.launches[i];
+    l.grid_per_xcd = tuned ? O.grid_choice[prec][i] : 0;
+    l.run_tile(tuned ? O.tile_choice[prec][i] : TILE_64x64, *tab, p0, sigma, prec, stream);
+  };
   k_fill(sigma, 0.0, O.npsi, stream);
   if (!O.profile) {
-    for (auto& l : O.launches) l.run(*tab, p0, sigma, prec, stream);
+    for (size_t i = 0; i < O.launches.size(); ++i) launch(i);
     return;
   }
   while (O.events.size() < O.launches.size() + 1) O.events.push_back(ev_create());
   ev_record(O.events[0], stream);
   for (size_t i = 0; i < O.launches.size(); ++i) {
-    O.launches[i].run(*tab, p0, sigma, prec, stream);
+    launch(i);
     ev_record(O.events[i + 1], stream);
   }
   for (size_t i = 0; i < O.launches.size(); ++i) O.prof_ms += ev_elapsed_ms(O.events[i], O.events[i + 1]);
   O.prof_launches += (int64_t)O.launches.size();
   ++O.prof_calls;
+}
+
+void autotune_launches(size_t nl, const std::function<void(const std::vector<int>&, const std::vector<int64_t>&,
+                                                           std::vector<double>&)>& run_all,
+                       std::vector<int>& tiles, std::vector<int64_t>& grids, double& ms_default, double& ms_best) {
+  std::vector<double> ms(nl), best(nl, 1e300);
+  tiles.assign(nl, TILE_64x64);
+  grids.assign(nl, 0);
+  std::vector<int> tv(nl);
+  std::vector<int64_t> gv(nl, 0);
+  ms_default = 0;
+  for (int t = 0; t < NTILE; ++t) {
+    std::fill(tv.begin(), tv.end(), t);
+    run_all(tv, gv, ms);  // warm-up (uploads this shape)
+    run_all(tv, gv, ms);
+    for (size_t i = 0; i < nl; ++i) {
+      if (t == TILE_64x64) ms_default += ms[i];
+      if (ms[i] < best[i]) {
+        best[i] = ms[i];
+        tiles[i] = t;
+      }
+    }
+  }
+  // persistent grid (8 workgroups per CU, 32 CUs per XCD) on the chosen shapes
+  std::fill(gv.begin(), gv.end(), int64_t(256));
+  run_all(tiles, gv, ms);
+  ms_best = 0;
+  for (size_t i = 0; i < nl; ++i) {
+    if (ms[i] < 0.97 * best[i]) {
+      best[i] = ms[i];
+      grids[i] = 256;
+    }
+    ms_best += best[i];
+  }
+}
+
+void sigma_autotune(Ops& O, int prec, void* stream) {
+  DMRG_CHECK(prec == P_F64 || prec == P_F32 || prec == P_BF16X3, DMRG_EINVAL, "unknown precision");
+  const size_t nl = O.launches.size();
+  double* psi = (double*)dev_alloc(sizeof(double) * (size_t)O.npsi);
+  double* sig = (double*)dev_alloc(sizeof(double) * (size_t)O.npsi);
+  k_fill(psi, 1.0 / std::sqrt((double)O.npsi), O.npsi, stream);
+  DevTable* tab = O.tab.get();
+  const void* p0 = psi;
+  if (prec != P_F64) {
+    make_reduced_copies(O, stream);
+    k_d2f(psi, O.psi32, O.npsi, stream);
+    tab = O.tab32.get();
+    p0 = O.psi32;
+  }
+  while (O.events.size() < nl + 1) O.events.push_back(ev_create());
+  auto run_all = [&](const std::vector<int>& tiles, const std::vector<int64_t>& grids, std::vector<double>& ms) {
+    k_fill(sig, 0.0, O.npsi, stream);
+    ev_record(O.events[0], stream);
+    for (size_t i = 0; i < nl; ++i) {
+      O.launches[i].grid_per_xcd = grids[i];
+      O.launches[i].run_tile(tiles[i], *tab, p0, sig, prec, stream);
+      ev_record(O.events[i + 1], stream);
+    }
+    for (size_t i = 0; i < nl; ++i) ms[i] = ev_elapsed_ms(O.events[i], O.events[i + 1]);
+  };
+  try {
+    autotune_launches(nl, run_all, O.tile_choice[prec], O.grid_choice[prec], O.tune_ms_default[prec],
+                      O.tune_ms_best[prec]);
+  } catch (...) {
+    dev_free(psi);
+    dev_free(sig);
+    throw;
+  }
+  dev_sync(stream);
+  dev_free(psi);
+  dev_free(sig);
+  // keep the device task lists of the shapes in use (64x64 serves untuned precisions)
+  for (size_t i = 0; i < nl; ++i) {
+    bool keep[NTILE] = {true, false, false, false};
+    for (int q = 0; q < 3; ++q)
+      if (O.tile_choice[q].size() == nl) keep[O.tile_choice[q][i]] = true;
+    for (int t = 0; t < NTILE; ++t)
+      if (!keep[t]) O.launches[i].release_tile(t);
+  }
 }
 
 // diag(H): families whose effective left and right operators conserve the

@@ -67,6 +67,12 @@ struct Ops {
   // stats
   double flops_r = 0, flops_l = 0, build_seconds = 0, build_flops = 0, op_bytes = 0;
   int64_t ngemm_r = 0, ngemm_l = 0, nterms = 0;
+  // launch shapes per precision chosen by the autotuner (default: 64x64 tiles,
+  // one workgroup per job); results do not depend on them
+  std::vector<int> tile_choice[3];
+  std::vector<int64_t> grid_choice[3];
+  double tune_ms_default[3] = {0, 0, 0}, tune_ms_best[3] = {0, 0, 0};
+  uint64_t serial = 0;                // unique per build (batched plans key on it)
   // live kernel timing (HIP events around every GEMM launch of sigma)
   bool profile = false;
   std::vector<void*> events;
@@ -89,6 +95,16 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
                                const double* data, void* stream, const BuildOptions& opt);
 
 void sigma_run(Ops& ops, const double* psi, double* sigma, int prec, void* stream);
+// Time every tile shape (then a persistent grid) on every launch of one sigma
+// call in precision prec and keep the fastest per launch.  Synchronous.
+void sigma_autotune(Ops& ops, int prec, void* stream);
+
+// Autotuner core shared with the batched plan: run_all(tile_of_launch,
+// grid_of_launch, ms_out) issues one full sigma sequence and returns per-launch
+// milliseconds; the tuner picks the fastest shape per launch.
+void autotune_launches(size_t nl, const std::function<void(const std::vector<int>&, const std::vector<int64_t>&,
+                                                           std::vector<double>&)>& run_all,
+                       std::vector<int>& tiles, std::vector<int64_t>& grids, double& ms_default, double& ms_best);
 void diag_run(Ops& ops, double* diag, void* stream);
 // FP32 copies of the sigma operators (idempotent; synchronous)
 void make_reduced_copies(Ops& ops, void* stream);

@@ -37,5 +37,6 @@ def test_binding_loads_and_rejects_bad_arguments():
     from paper_2311_02854_amd import binding
     lib = binding.load()
     assert lib.dmrg_sigma(None, None, None, None, 0) == -1
-    assert lib.dmrg_build_ops(None, None, None, None) == -1
+    assert lib.dmrg_build_ops(None, None, None, None, None) == -1
+    assert lib.dmrg_sigma_batched(None, 0, None, None, None, 0, 0) == -1
     assert lib.dmrg_last_error(None) == b"null context"
