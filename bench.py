@@ -113,6 +113,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2311_02854_amd", "csrc", "kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_f64_sigma_K73_D2000_pmc.md")
+
+
+def measured_traffic(config, precision):
+    """HBM bytes per sigma call from the committed rocprofv3 PMC summary
+    (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor, KiB -> bytes), or
+    None if there is none for this workload or the GEMM kernel source changed
+    since the counters were taken."""
+    import hashlib
+    if config != "5" or precision != "fp64" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_call"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(ctx):
     """The oracle (O1) timed on the host on a bounded sample of the workload."""
     import synth
@@ -197,6 +223,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=sorted(PREC_ID),
                     help="arithmetic of the sigma contraction (psi and sigma stay binary64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--davidson", action="store_true",
                     help="also time Davidson to 1e-6 Eh (plain FP64+diagonal vs FP32+learned preconditioner)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_02854_amd", "data", "precond_mlp.npy"),
@@ -242,6 +269,12 @@ def main():
         del a, b
         log("[bench] copy probe: 3 x 1 GiB device-to-device copies done")
     prec = PREC_ID[args.precision]
+    tune = None
+    if not args.no_tune:
+        t0 = time.time()
+        ms0, ms1 = ops.autotune(prec)
+        tune = {"ms_default_shapes": ms0, "ms_tuned": ms1, "tune_s": time.time() - t0}
+        log(f"[bench] autotune: {ms0:.1f} ms/call with 64x64 tiles -> {ms1:.1f} ms/call ({time.time() - t0:.1f} s)")
     for i in range(args.warmup):
         ops.sigma(x.data_ptr(), y.data_ptr(), prec)
         torch.cuda.synchronize()
@@ -270,9 +303,10 @@ def main():
                                 f"dots at sites ({k + 1},{k + 2}) of 1..K, seeded integrals and MPS"),
                    "n_psi": int(st["n_psi"]), "psi_blocks": int(st["n_blocks"]), "terms": int(st["n_terms"]),
                    "gemms_per_call": int(st["n_rgemm"] + st["n_lgemm"]), "tflop_per_call": flops / 1e12,
-                   "build_ops_s": t_build, "operator_GB": st["op_bytes"] / 1e9},
+                   "build_ops_s": t_build, "operator_GB": st["op_bytes"] / 1e9, "autotune": tune},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAKS[args.precision], "unit": "TFLOP/s",
-                     "frac": (achieved / PEAKS[args.precision]) if achieved else None, "traffic": None,
+                     "frac": (achieved / PEAKS[args.precision]) if achieved else None,
+                     "traffic": measured_traffic(args.config, args.precision), "traffic_unit": "bytes per sigma call",
                      "kernel": f"gemm_kernel<{args.precision}>", "kernel_ms_per_call": kern_ms,
                      "launches_per_call": prof["prof_launches"] / max(1, prof["prof_sigma_calls"])},
     }

@@ -44,6 +44,8 @@ enum : int32_t { GF_TRANS_A = 1, GF_TRANS_B = 2, GF_IDENT_A = 4 };
 // operand precision (the sigma output; buffer 1 always is)
 enum : int32_t { GT_ACCUM = 1, GT_C64 = 2 };
 // Workgroup tile shapes of the grouped GEMM (rows x columns of C)
+// (larger tiles, 64x128 up to 128x128, were measured slower on this GPU:
+// their register tiles drop the occupancy to 1-2 waves per SIMD)
 enum : int { TILE_64x64 = 0, TILE_32x32 = 1, TILE_64x32 = 2, TILE_32x64 = 3, NTILE = 4 };
 inline int tile_rows(int t) { return (t == TILE_32x32 || t == TILE_32x64) ? 32 : 64; }
 inline int tile_cols(int t) { return (t == TILE_32x32 || t == TILE_64x32) ? 32 : 64; }

@@ -118,9 +118,9 @@ constexpr int BK = 32, NT = 256;
 // Operand precision policies.  FP64 and FP32 stage op(A) and op(B) tiles in
 // LDS k-major ([k][row], rows contiguous) and feed 16x16x4 MFMAs one element
 // per lane.  BF16x3 reads FP32 operands, splits every value while staging into
-// hi = bf16(x) and lo = bf16(x - hi) (round to nearest even), stores them
-// row-major ([row][k], k contiguous) and accumulates hi*hi + hi*lo + lo*hi in
-// FP32 with 16x16x32 MFMAs.
+// hi = bf16(x) and lo = bf16(x - hi) (round to nearest even, two values per
+// conversion), stores them row-major ([row][k], k contiguous) and accumulates
+// hi*hi + hi*lo + lo*hi in FP32 with 16x16x32 MFMAs.
 struct PolF64 {
   using T = double;
   using Acc = d4_t;
@@ -166,11 +166,29 @@ __device__ __forceinline__ f4_t mfma32(bf8_t a, bf8_t b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// bf16 bits of x rounded to nearest, ties to even (finite x)
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Every operand and output of the GEMM kernels lives in global memory: loads
+// and stores go through address-space-1 pointers so that they compile to
+// global (not flat) instructions, which do not count against the LDS wait
+// counter the MFMA loop waits on.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(GLOBAL T*)p = v;
+}
+
+typedef float f2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+
+// Split x = hi + lo of two floats into packed bf16 pairs: hi = bf16(x),
+// lo = bf16(x - hi), both rounded to nearest even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ void split_bf16x2(f2_t x, uint32_t& hi, uint32_t& lo) {
+  hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, b2_t));
+  const f2_t hf = {__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u)};
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(x - hf, b2_t));
 }
 
 // Task of a job: the bucket table narrows the search to the tasks that
@@ -204,6 +222,7 @@ struct Opnd {
   int r_inc, k_inc;  // increments per element (one of them is 0)
   int rows, K;       // valid extent (rows counted from the tile origin)
   T scale;
+  int64_t s2;        // split staging: distance from a pair's first to its second element
 };
 
 template <int ROWS, typename T>
@@ -241,7 +260,7 @@ __device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E], b
   for (int it = 0; it < E; ++it) {
     const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
     ok[it] = (r < o.rows) & (k < o.K);
-    v[it] = *(ok[it] ? p + it * o.step_it : o.origin);
+    v[it] = gld(ok[it] ? p + it * o.step_it : o.origin);
   }
 }
 
@@ -252,17 +271,62 @@ __device__ __forceinline__ void opnd_store(const Opnd<T>& o, const T (&v)[E], co
     L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = ok[it] ? v[it] * o.scale : T(0);
 }
 
+// Split-BF16 staging: every thread owns E/2 pairs of k-consecutive elements
+// (k contiguous in memory: 16 threads per row, 16 rows per pass; else r
+// fastest, 2*256/ROWS k per pass), so that each pair converts with one
+// instruction and lands in LDS ([row][k]) as one 32-bit store per half.
+template <int ROWS>
+__device__ __forceinline__ void opnd_setup_split(Opnd<float>& o, const float* X, int64_t sr, int64_t sk, int r0,
+                                                 int rows, int K, float scale) {
+  const int tid = threadIdx.x;
+  if (sk == 1) {
+    o.r_first = tid >> 4;
+    o.k_first = 2 * (tid & 15);
+    o.r_inc = NT / 16;
+    o.k_inc = 0;
+    o.step_it = (NT / 16) * sr;
+  } else {
+    o.r_first = tid % ROWS;
+    o.k_first = 2 * (tid / ROWS);
+    o.r_inc = 0;
+    o.k_inc = 2 * NT / ROWS;
+    o.step_it = (2 * NT / ROWS) * sk;
+  }
+  o.s2 = sk;
+  o.origin = X;
+  o.base = X + (int64_t)(r0 + o.r_first) * sr + (int64_t)o.k_first * sk;
+  o.step_k = (int64_t)BK * sk;
+  o.rows = rows - r0;
+  o.K = K;
+  o.scale = scale;
+}
+
+template <int E>
+__device__ __forceinline__ void opnd_load_split(const Opnd<float>& o, int k0, float (&v)[E], bool (&ok)[E]) {
+  const float* p = o.base + (int64_t)(k0 / BK) * o.step_k;
+#pragma unroll
+  for (int it = 0; it < E / 2; ++it) {
+    const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
+    const bool rv = r < o.rows;
+    ok[2 * it] = rv & (k < o.K);
+    ok[2 * it + 1] = rv & (k + 1 < o.K);
+    const float* q = p + it * o.step_it;
+    v[2 * it] = gld(ok[2 * it] ? q : o.origin);
+    v[2 * it + 1] = gld(ok[2 * it + 1] ? q + o.s2 : o.origin);
+  }
+}
+
 template <int E, int LD>
 __device__ __forceinline__ void opnd_store_split(const Opnd<float>& o, const float (&v)[E], const bool (&ok)[E],
                                                  uint16_t (*H)[LD], uint16_t (*Lo)[LD]) {
 #pragma unroll
-  for (int it = 0; it < E; ++it) {
-    const float x = ok[it] ? v[it] * o.scale : 0.0f;
-    const uint16_t h = bf16_rne(x);
-    const uint16_t l = bf16_rne(x - __uint_as_float((uint32_t)h << 16));
+  for (int it = 0; it < E / 2; ++it) {
     const int r = o.r_first + it * o.r_inc, k = o.k_first + it * o.k_inc;
-    H[r][k] = h;
-    Lo[r][k] = l;
+    const f2_t x = {ok[2 * it] ? v[2 * it] * o.scale : 0.0f, ok[2 * it + 1] ? v[2 * it + 1] * o.scale : 0.0f};
+    uint32_t hi, lo;
+    split_bf16x2(x, hi, lo);
+    *reinterpret_cast<uint32_t*>(&H[r][k]) = hi;
+    *reinterpret_cast<uint32_t*>(&Lo[r][k]) = lo;
   }
 }
 
@@ -275,7 +339,7 @@ struct Step {
 // Grouped GEMM over a task list (see device.h).  Operand buffers hold P::T;
 // the output is P::T, or binary64 for tasks flagged GT_C64 (buffer 1 is p1).
 template <class P, int WM, int WN>
-__global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ tasks, const XcdMap map,
+__global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ tasks, const XcdMap map,
                                                   const GContrib* __restrict__ contribs,
                                                   const int* __restrict__ bucket_all,
                                                   typename P::T* const* __restrict__ table,
@@ -325,7 +389,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
       for (int t = 0; t < Cb.nred; ++t) {
         const T* B = opp(Cb.b_buf) + Cb.b_off + batch * Cb.b_bstride + (int64_t)t * Cb.b_rstride;
         T alpha = (T)Cb.alpha;
-        if (Cb.s_buf >= 0) alpha *= opp(Cb.s_buf)[Cb.s_off + batch * Cb.s_bstride + (int64_t)t * Cb.s_rstride];
+        if (Cb.s_buf >= 0) alpha *= gld(opp(Cb.s_buf) + Cb.s_off + batch * Cb.s_bstride + (int64_t)t * Cb.s_rstride);
 #pragma unroll
         for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
@@ -334,7 +398,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
             for (int v = 0; v < 4; ++v) {
               int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
               if (r < Tk.M && c < Tk.N)
-                acc[mi][ni][v] += alpha * (tb ? B[(int64_t)c * Cb.ldb + r] : B[(int64_t)r * Cb.ldb + c]);
+                acc[mi][ni][v] += alpha * gld(tb ? B + (int64_t)c * Cb.ldb + r : B + (int64_t)r * Cb.ldb + c);
             }
       }
     }
@@ -350,11 +414,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
       const T* A = opp(Cb.a_buf) + Cb.a_off + batch * Cb.a_bstride + (int64_t)s.t * Cb.a_rstride;
       const T* B = opp(Cb.b_buf) + Cb.b_off + batch * Cb.b_bstride + (int64_t)s.t * Cb.b_rstride;
       T alpha = (T)Cb.alpha;
-      if (Cb.s_buf >= 0) alpha *= opp(Cb.s_buf)[Cb.s_off + batch * Cb.s_bstride + (int64_t)s.t * Cb.s_rstride];
+      if (Cb.s_buf >= 0) alpha *= gld(opp(Cb.s_buf) + Cb.s_off + batch * Cb.s_bstride + (int64_t)s.t * Cb.s_rstride);
       const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
       // op(A)(m, k): stored M x K (lda) or K x M;  op(B)(k, n) seen as (n, k)
-      opnd_setup<BM>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
-      opnd_setup<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
+      if constexpr (P::split) {
+        opnd_setup_split<BM>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
+        opnd_setup_split<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
+      } else {
+        opnd_setup<BM>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
+        opnd_setup<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
+      }
     };
     Step cur{first_from(Tk.contrib_begin), 0, 0, 0};
     if (cur.ci < Tk.contrib_end) {
@@ -363,8 +432,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
       setup(cur, oa, ob);
       T ra[EA], rb[EB];
       bool ka[EA], kb[EB];
-      opnd_load(oa, 0, ra, ka);
-      opnd_load(ob, 0, rb, kb);
+      auto load = [&](int k0) {
+        if constexpr (P::split) {
+          opnd_load_split(oa, k0, ra, ka);
+          opnd_load_split(ob, k0, rb, kb);
+        } else {
+          opnd_load(oa, k0, ra, ka);
+          opnd_load(ob, k0, rb, kb);
+        }
+      };
+      load(0);
       for (;;) {
         if constexpr (P::split) {
           opnd_store_split(oa, ra, ka, sm.Ah, sm.Al);
@@ -391,10 +468,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
             setup(nxt, oa, ob);
           }
         }
-        if (more) {
-          opnd_load(oa, nxt.k0, ra, ka);
-          opnd_load(ob, nxt.k0, rb, kb);
-        }
+        if (more) load(nxt.k0);
         if constexpr (P::split) {
           // one 16x16x32 step covers the whole k tile (entries past K are 0)
           if (any) {
@@ -473,8 +547,8 @@ __global__ __launch_bounds__(NT) void gemm_kernel(const GTask* __restrict__ task
             if (r < Tk.M && c < Tk.N) {
               auto* dst = Cp + (int64_t)r * Tk.ldc + c;
               auto val = (decltype(*dst + 0))acc[mi][ni][v];
-              if (Tk.accumulate & GT_ACCUM) val += *dst;
-              *dst = val;
+              if (Tk.accumulate & GT_ACCUM) val += gld(dst);
+              gst(dst, val);
             }
           }
     };
@@ -502,6 +576,7 @@ static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, c
     case TILE_32x64:
       hipLaunchKernelGGL((gemm_kernel<P, 1, 2>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
       break;
+
     default:
       throw Error(DMRG_EINVAL, "unknown GEMM tile shape");
   }

@@ -948,7 +948,7 @@ void sigma_autotune(Ops& O, int prec, void* stream) {
   dev_free(sig);
   // keep the device task lists of the shapes in use (64x64 serves untuned precisions)
   for (size_t i = 0; i < nl; ++i) {
-    bool keep[NTILE] = {true, false, false, false};
+    bool keep[NTILE] = {true};
     for (int q = 0; q < 3; ++q)
       if (O.tile_choice[q].size() == nl) keep[O.tile_choice[q][i]] = true;
     for (int t = 0; t < NTILE; ++t)
