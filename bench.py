@@ -172,35 +172,35 @@ def cpu_baseline(ctx):
 def davidson_leg(ops, psi, mlp_path):
     """Davidson time to 1e-6 Eh from the seeded start vector.
 
-    Solvers: FP32 sigma (FP64 polish) with the learned preconditioner, the same with
-    the diagonal preconditioner, and plain FP64 sigma with the diagonal one.  E_ref is
-    the energy of the first solver converged to ||r|| <= 1e-5 with FP64 sigma; its
-    time to E_ref + 1e-6 comes from its trace, the other two stop there.  The FP32
-    operator copies and the per-bond feature tables are built before the timed runs
-    (they belong to the operator build)."""
+    Solvers: split-BF16 sigma (FP64 polish) with the learned preconditioner, the same
+    with the diagonal preconditioner, and plain FP64 sigma with the diagonal one.
+    E_ref is the energy of the first solver converged to ||r|| <= 1e-5 with FP64
+    sigma; its time to E_ref + 1e-6 comes from its trace, the other two stop there.
+    The FP32 operator copies and the per-bond feature tables are built before the
+    timed runs (they belong to the operator build)."""
     import torch
     w = np.load(mlp_path).astype(np.float32)
     y = torch.empty(len(psi), dtype=torch.float64, device="cuda")
     x = torch.from_numpy(psi).cuda()
     t = torch.empty_like(y)
-    ops.sigma(x.data_ptr(), y.data_ptr(), 1)                           # FP32 operator copies
+    ops.sigma(x.data_ptr(), y.data_ptr(), 2)                           # FP32 operator copies
     ops.mlp_apply(w, x.data_ptr(), y.data_ptr(), 0.0, t.data_ptr())    # per-bond feature tables
     torch.cuda.synchronize()
     del t
     out = {"start": "seeded Gaussian psi (the bench input)", "mlp_weights": os.path.relpath(mlp_path, ROOT)}
-    log("[bench] davidson fp32_mlp (reference run) ...")
+    log("[bench] davidson bf16x3_mlp (reference run) ...")
     x = torch.from_numpy(psi).cuda()
-    eref, st = ops.davidson(x.data_ptr(), trace=4000, precision=1, precond=1, mlp_weights=w,
+    eref, st = ops.davidson(x.data_ptr(), trace=4000, precision=2, precond=1, mlp_weights=w,
                             tol_residual=1e-5, max_iter=2000)
     tr = st["trace"]
     hit = np.nonzero((tr[:, 1] <= eref + 1e-6) & (tr[:, 3] == 0))[0]
     out["E_ref"] = eref
-    out["fp32_mlp"] = {"seconds_to_1e-6": float(tr[hit[0], 0]), "iterations_to_1e-6": int(hit[0] + 1),
+    out["bf16x3_mlp"] = {"seconds_to_1e-6": float(tr[hit[0], 0]), "iterations_to_1e-6": int(hit[0] + 1),
                        "switch_iter": st["switch_iter"], "mlp_fallbacks": st["mlp_fallbacks"],
                        "seconds_total": st["seconds"], "iterations_total": st["iterations"],
                        "residual": st["residual"], "converged": st["converged"]}
-    log(f"[bench] davidson fp32_mlp: {out['fp32_mlp']}")
-    for name, kw in (("plain_fp64_diag", {}), ("fp32_diag", {"precision": 1})):
+    log(f"[bench] davidson bf16x3_mlp: {out['bf16x3_mlp']}")
+    for name, kw in (("plain_fp64_diag", {}), ("bf16x3_diag", {"precision": 2})):
         log(f"[bench] davidson {name} ...")
         x = torch.from_numpy(psi).cuda()
         e, st = ops.davidson(x.data_ptr(), e_ref=eref, e_tol=1e-6, stop_at_ref=1, max_iter=2000,
@@ -209,8 +209,8 @@ def davidson_leg(ops, psi, mlp_path):
                      "fp64_sigma_calls": st["sigma_fp64"], "switch_iter": st["switch_iter"], "E-E_ref": e - eref}
         log(f"[bench] davidson {name}: {out[name]}")
     t0 = out["plain_fp64_diag"]["seconds_to_1e-6"]
-    t1 = out["fp32_mlp"]["seconds_to_1e-6"]
-    out["speedup_fp32_mlp_vs_plain"] = (t0 / t1) if (t0 and t0 > 0 and t1 and t1 > 0) else None
+    t1 = out["bf16x3_mlp"]["seconds_to_1e-6"]
+    out["speedup_bf16x3_mlp_vs_plain"] = (t0 / t1) if (t0 and t0 > 0 and t1 and t1 > 0) else None
     return out
 
 
@@ -224,8 +224,10 @@ def main():
                     help="arithmetic of the sigma contraction (psi and sigma stay binary64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--x-budget-gb", type=float, default=0.0,
+                    help="R-step scratch per slot in GB (0: library default)")
     ap.add_argument("--davidson", action="store_true",
-                    help="also time Davidson to 1e-6 Eh (plain FP64+diagonal vs FP32+learned preconditioner)")
+                    help="also time Davidson to 1e-6 Eh (plain FP64+diagonal vs split-BF16+learned preconditioner)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_02854_amd", "data", "precond_mlp.npy"),
                     help="learned preconditioner weights for --davidson")
     ap.add_argument("--copy-probe", action="store_true",
@@ -253,7 +255,7 @@ def main():
     log(f"[bench] synthetic inputs {time.time() - t0:.1f} s, n_psi={len(psi)}")
     ctx = gpu_context(0)
     t0 = time.time()
-    ops = ctx.build_ops(ints, mps)
+    ops = ctx.build_ops(ints, mps, x_budget=int(args.x_budget_gb * 1e9))
     t_build = time.time() - t0
     st = ops.stats()
     log(f"[bench] build_ops {t_build:.1f} s ({st['build_flops'] / 1e12:.1f} TFLOP renormalization), "

@@ -132,7 +132,8 @@ typedef struct {
   double seconds_to_ref;   /* time to first Ritz value <= e_ref + e_tol (or -1) */
   int iters_to_ref;
   int mlp_fallbacks;       /* iterations that used the diagonal correction although
-                              precond == 1 (the MLP step was judged by the FP64 residual) */
+                              precond == 1: after three model steps whose FP64 residual
+                              exceeded twice the best one seen (or was not finite) */
   int switch_iter;         /* iteration at which FP64 sigma took over (-1: never reduced) */
   int trace_len;           /* rows written to opts->trace */
 } dmrg_davidson_stats;
@@ -145,7 +146,7 @@ const char* dmrg_last_error(const dmrg_ctx* ctx);
 
 /* Scratch budgets of dmrg_build_ops (0 selects the default). */
 typedef struct {
-  size_t x_budget_bytes;   /* each of the two R-step scratch slots of sigma (default 4 GiB):
+  size_t x_budget_bytes;   /* each of the two R-step scratch slots of sigma (default 16 GiB):
                               a smaller budget splits sigma into more launches */
   size_t t_budget_bytes;   /* renormalization scratch per growth step (default 2 GiB) */
 } dmrg_build_opts;
@@ -224,9 +225,9 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts* opts);
  * Features of element i, in block (il, n1, n2, ir) of a bond with dots at
  * sites (k, k+1), theta the Ritz value and r the residual:
  *   0      clamp((H_ii - theta) / s_h, -8, 8),  s_h = rms over i of (H_ii - theta)
- *   1      asinh((H_ii - theta) / 0.01) / 8      (energies in Eh)
+ *   1      asinh((H_ii - theta) / ||r||_2) / 4
  *   2      clamp(r_i / s_r, -8, 8),              s_r = rms over i of r_i
- *   3      asinh(|r_i| / s_r) / 4
+ *   3      log10(||r||_2) / 4
  *   4, 5   (q_alpha, q_beta)(il) - (N_alpha, N_beta) * k / K, over sqrt(K)
  *   6, 7   the right block's electrons (N - q(ir)) - N * (K - k - 2) / K, over sqrt(K)
  *   8..11  one-hot n1;  12..15 one-hot n2
@@ -249,22 +250,29 @@ int dmrg_mlp_init(float* weights, uint64_t seed);
  * preconditioner from psi0 (device, n_psi; not modified) for at most max_iter
  * sigma calls and, at every iteration, draws per_iter element indices
  * (seeded) and records for each: the features f_i, the diagonal correction
- * d_i, and the target s*e_i, where e = psi_ref - x <x|psi_ref> is the part of
- * the reference eigenvector psi_ref (device, normalised, sign aligned with x)
- * orthogonal to the Ritz vector x, and s = <d,e>/<e,e> is the scale that best
- * matches d.  Host outputs of capacity cap pairs: feat[cap][NFEAT], dcorr[cap],
+ * d_i, and the target s*e_i, where e is the part of the reference eigenvector
+ * psi_ref (device, normalised) orthogonal to the current Davidson subspace
+ * (which holds the Ritz vector) -- the direction the next correction has to
+ * supply -- and s = <d,e>/<e,e> is the scale that best matches d.  Host outputs of capacity cap pairs: feat[cap][NFEAT], dcorr[cap],
  * target[cap]; *n_out receives the number written.  Synchronous. */
 int dmrg_mlp_collect(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi0, const double* psi_ref,
                      int max_iter, int per_iter, uint64_t seed, int64_t cap, float* feat,
                      float* dcorr, float* target, int64_t* n_out);
 
-/* Fit the gains by Adam on the loss mean_i (g(f_i) d_i - target_i)^2 with the
- * GPU training kernels.  Host inputs of n pairs (as written by
- * dmrg_mlp_collect); weights (host) are read as the start point and
- * overwritten with the result; loss_before/after (may be NULL) receive the
- * loss over all n pairs.  Synchronous. */
+/* Fit the gains by Adam with the GPU training kernels, on host inputs of n
+ * pairs as written by dmrg_mlp_collect.  group == 0: loss mean_i (g(f_i) d_i -
+ * target_i)^2 over minibatches of `batch` pairs.  group > 0: the pairs form
+ * groups of `group` consecutive entries (one Davidson iteration each; n a
+ * multiple of group) and the loss of a group is 1 - cos^2(g.d, target), the
+ * misalignment of the correction with the ideal one, which Davidson's
+ * subspace step does not see the scale of; one group per step (batch unused).
+ * A seeded tenth of the pairs (groups) is held out, and of the start point and
+ * the weights after each epoch the one with the lowest held-out loss is kept.
+ * weights (host) are read as the start point and overwritten with the result;
+ * loss_before/after (may be NULL) receive the loss over all data.
+ * Synchronous. */
 int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dcorr,
-                   const float* target, int epochs, int batch, float lr, uint64_t seed,
+                   const float* target, int group, int epochs, int batch, float lr, uint64_t seed,
                    float* weights, double* loss_before, double* loss_after);
 
 /* One preconditioner application on the device: t = g(f) * d for residual r

@@ -97,7 +97,8 @@ def load(path=None):
     lib.dmrg_mlp_nweights.argtypes = []
     lib.dmrg_mlp_init.argtypes = [fp, C.c_uint64]
     lib.dmrg_mlp_collect.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_uint64, C.c_int64, fp, fp, fp, i64p]
-    lib.dmrg_mlp_train.argtypes = [vp, C.c_int64, fp, fp, fp, C.c_int, C.c_int, C.c_float, C.c_uint64, fp, dp, dp]
+    lib.dmrg_mlp_train.argtypes = [vp, C.c_int64, fp, fp, fp, C.c_int, C.c_int, C.c_int, C.c_float, C.c_uint64, fp,
+                                   dp, dp]
     lib.dmrg_mlp_apply.argtypes = [vp, vp, fp, vp, vp, C.c_double, vp]
     return lib
 
@@ -248,16 +249,17 @@ def mlp_init(lib, seed):
     return w
 
 
-def mlp_train(ctx, feat, dcorr, target, weights, epochs=10, batch=4096, lr=1e-3, seed=0):
-    """Train in place on the GPU; returns (loss_before, loss_after)."""
+def mlp_train(ctx, feat, dcorr, target, weights, epochs=10, batch=4096, lr=1e-3, seed=0, group=0):
+    """Train in place on the GPU; returns (loss_before, loss_after).  group > 0 selects the
+    per-group direction loss (groups of `group` consecutive pairs)."""
     feat = np.ascontiguousarray(feat, np.float32)
     dcorr = np.ascontiguousarray(dcorr, np.float32)
     target = np.ascontiguousarray(target, np.float32)
     assert weights.dtype == np.float32 and weights.flags.c_contiguous
     lb, la = C.c_double(), C.c_double()
     ctx._check(ctx.lib.dmrg_mlp_train(ctx.h, len(dcorr), _p(feat, C.c_float), _p(dcorr, C.c_float),
-                                      _p(target, C.c_float), int(epochs), int(batch), float(lr), int(seed),
-                                      _p(weights, C.c_float), C.byref(lb), C.byref(la)))
+                                      _p(target, C.c_float), int(group), int(epochs), int(batch), float(lr),
+                                      int(seed), _p(weights, C.c_float), C.byref(lb), C.byref(la)))
     return lb.value, la.value
 
 

@@ -259,11 +259,13 @@ int dmrg_mlp_collect(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi0, con
   });
 }
 
-int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dcorr, const float* target, int epochs,
-                   int batch, float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after) {
+int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dcorr, const float* target, int group,
+                   int epochs, int batch, float lr, uint64_t seed, float* weights, double* loss_before,
+                   double* loss_after) {
   if (!ctx || !feat || !dcorr || !target || !weights) return DMRG_EINVAL;
   return guarded(ctx, [&] {
-    dmrg::mlp_train(n, feat, dcorr, target, epochs, batch, lr, seed, weights, loss_before, loss_after, ctx->stream);
+    dmrg::mlp_train(n, feat, dcorr, target, group, epochs, batch, lr, seed, weights, loss_before, loss_after,
+                    ctx->stream);
     return (int)DMRG_OK;
   });
 }

@@ -70,7 +70,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   sig(Vp(0), Wp(0), prec);
   int iters = 1, iters64 = (prec == P_F64) ? 1 : 0, switch_iter = (prec == P_F64) ? -1 : 0;
   int m = 1;
-  double theta = 0, rn = 1e300, best_rn = 1e300, prev_rn = 1e300, prev_theta = 1e300;
+  double theta = 0, rn = 1e300, best_rn = 1e300, prev_theta = 1e300, best_any = 1e300;
   int stagnant = 0, ntrace = 0;
   bool have_prev = false, converged = false, reached = false;
   double t_ref = -1;
@@ -115,7 +115,6 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     k_lincomb(W.p, n, m, dy, n, hx.p, stream);
     k_copy(hx.p, r.p, n, stream);
     k_axpby(-theta, x.p, 1.0, r.p, n, stream);
-    prev_rn = rn;
     rn = std::sqrt(ddot(r.p, r.p, n, dvals, stream));
     if (opt.trace && ntrace < opt.trace_cap) {
       double* row = opt.trace + 4 * (int64_t)ntrace++;
@@ -124,8 +123,11 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       row[2] = rn;
       row[3] = prec;
     }
-    // the MLP step is judged by the FP64 residual it produced
-    if (used_mlp && !(rn < prev_rn)) ++mlp_fail;
+    // the MLP step is judged by the FP64 residual it produced: a step that
+    // more than doubles the best residual seen, or is not finite, counts
+    // against the model (Davidson residuals are not monotone)
+    if (used_mlp && !(rn <= 2.0 * best_any)) ++mlp_fail;
+    if (std::isfinite(rn)) best_any = std::min(best_any, rn);
     if (std::isfinite(opt.e_ref) && t_ref < 0 && prec == P_F64 && theta <= opt.e_ref + opt.e_tol) {
       t_ref = wall_seconds() - t_start;
       it_ref = iters;
@@ -152,6 +154,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       have_prev = false;
       used_mlp = false;
       rn = 1e300;
+      best_any = 1e300;
       rebuild_G();
       continue;
     }
@@ -161,7 +164,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     }
     // correction vector
     dev_h2d(dth, &theta, sizeof(double));
-    if (hook) hook(x.p, r.p, dg.p, dth, iters);
+    if (hook) hook(x.p, r.p, dg.p, dth, V.p, m, iters);
     used_mlp = opt.precond == 1 && mlp_fail < 3;
     if (used_mlp)
       mlp_precondition(O, r.p, dg.p, dth, t.p, opt.mlp_weights, stream);

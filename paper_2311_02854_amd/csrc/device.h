@@ -124,7 +124,7 @@ void k_gather_diag(const double* src, const int64_t* meta, int nblk, int64_t src
 // scale the per-member coefficient rows etc.: y[i] *= s
 void k_scale(double* y, double s, int64_t n, void* stream);
 // --- learned preconditioner (mlp.hip) --------------------------------------
-// scales[0] = rms(diag - theta), scales[1] = rms(r); part holds 2*256 doubles
+// scales[0] = rms(diag - theta), scales[1] = rms(r), scales[2] = ||r||_2; part holds 2*256 doubles
 void k_mlp_scales(const double* r, const double* diag, const double* theta, int64_t n, double* part,
                   double* scales, void* stream);
 // out_i = g(f_i) * r_i / (theta - diag_i) with the MLP weights w (device)
@@ -138,6 +138,9 @@ void k_mlp_gather_pairs(const int64_t* idx, int m, const double* r, const double
 void k_mlp_train_fwd(const float* w, const float* F, int64_t n, float* a1, float* a2, float* g, void* stream);
 void k_mlp_bwd_out(const float* w, const float* g, const float* d, const float* y, const float* a2, int64_t n,
                    float* dout, float* dz2, void* stream);
+// direction loss of one group of n samples (one block; see mlp.hip)
+void k_mlp_cos_grad(const float* w, const float* g, const float* d, const float* y, const float* a2, int64_t n,
+                    float* dout, float* dz2, float* loss, void* stream);
 void k_relu_mask(float* dz, const float* a, int64_t n, void* stream);
 void k_colsum(const float* X, const float* v, int64_t n, int ncol, float* out, void* stream);
 void k_sum_f(const float* x, int64_t n, float* out, void* stream);

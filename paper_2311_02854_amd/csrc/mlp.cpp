@@ -79,7 +79,7 @@ void mlp_prepare(Ops& O, void* stream) {
   O.mlp_stat = (float*)dev_alloc(sizeof(float) * stat.size());
   dev_h2d(O.mlp_stat, stat.data(), sizeof(float) * stat.size());
   O.mlp_part = (double*)dev_alloc(sizeof(double) * 2 * 256);
-  O.mlp_scales = (double*)dev_alloc(sizeof(double) * 2);
+  O.mlp_scales = (double*)dev_alloc(sizeof(double) * 4);
   (void)stream;
 }
 
@@ -112,18 +112,24 @@ int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_i
                     int64_t cap, float* feat, float* dcorr, float* target, void* stream) {
   mlp_prepare(O, stream);
   const int64_t n = O.npsi;
-  DBufD x0(n), e(n), d(n), sc(64);
+  DBufD x0(n), e(n), d(n), sc(64), dots(64);
   DBufF ff((size_t)per_iter * NF), fd(per_iter), fy(per_iter);
   int64_t* didx = (int64_t*)dev_alloc(sizeof(int64_t) * std::max(1, per_iter));
   k_copy(psi0, x0.p, n, stream);
   int64_t written = 0;
   std::vector<int64_t> idx(per_iter);
-  auto hook = [&](const double* x, const double* r, const double* diag, const double* theta_dev, int iter) {
+  auto hook = [&](const double* x, const double* r, const double* diag, const double* theta_dev, const double* V,
+                  int m_sub, int iter) {
     if (written >= cap) return;
-    // ideal correction: the part of psi_ref orthogonal to x, sign aligned
-    const double c = dot(x, psi_ref, n, sc.p, stream);
-    k_copy(x, e.p, n, stream);
-    k_axpby(c >= 0 ? 1.0 : -1.0, psi_ref, -std::fabs(c), e.p, n, stream);
+    (void)x;
+    // ideal correction: the part of psi_ref orthogonal to the current subspace
+    // (which holds the Ritz vector), i.e. what the next direction must supply;
+    // two projection passes
+    k_copy(psi_ref, e.p, n, stream);
+    for (int pass = 0; pass < 2; ++pass) {
+      k_multidot(V, n, m_sub, e.p, n, dots.p, stream);
+      k_sub_lincomb(V, n, m_sub, dots.p, n, e.p, stream);
+    }
     k_precond_diag(r, diag, theta_dev, FLOOR, d.p, n, stream);
     const double de = dot(d.p, e.p, n, sc.p, stream), ee = dot(e.p, e.p, n, sc.p, stream);
     const double dd = dot(d.p, d.p, n, sc.p, stream);
@@ -167,11 +173,27 @@ int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_i
   return written;
 }
 
-// Adam on the mean squared error of g(f) d - target.
-void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* target, int epochs, int batch,
-               float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after, void* stream) {
-  DMRG_CHECK(n > 0 && epochs >= 0 && batch > 0, DMRG_EINVAL, "training needs n > 0, epochs >= 0, batch > 0");
-  const int B = (int)std::min<int64_t>(batch, n);
+// Training by Adam.  Loss, for group == 0: mean_i (g(f_i) d_i - target_i)^2
+// over minibatches of `batch` pairs; for group > 0: the pairs form groups of
+// `group` consecutive entries (the samples of one Davidson iteration) and the
+// loss of a group is the direction loss 1 - cos^2(g.d, target), which does not
+// depend on the scale of the correction; one group per step.  A seeded tenth
+// of the pairs (of the groups) is held out; after every epoch the held-out loss
+// decides whether the weights are kept, starting from the given ones, so the
+// result is never worse on held-out data than the start (g = 1 for the
+// dmrg_mlp_init weights).
+void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* target, int group, int epochs,
+               int batch, float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after,
+               void* stream) {
+  DMRG_CHECK(n > 1 && epochs >= 0 && group >= 0 && (group > 0 || batch > 0), DMRG_EINVAL,
+             "training needs n > 1, epochs >= 0, and a batch or group size");
+  DMRG_CHECK(group == 0 || (n % group == 0 && n / group >= 2 && group <= (1 << 16)), DMRG_EINVAL,
+             "n must be a multiple of group, with at least two groups");
+  const bool cosl = group > 0;
+  // units: single pairs (MSE) or groups (direction loss)
+  const int64_t usz = cosl ? group : 1, nunit = n / usz;
+  const int64_t nval = std::max<int64_t>(1, nunit / 10), ntr = nunit - nval;
+  const int B = cosl ? group : (int)std::min<int64_t>(batch, ntr);
   const int nw = mlp_nweights();
   DBufF F((size_t)n * NF), Dv(n), Y(n), g(n), sq(n);
   DBufF Fb((size_t)B * NF), Db(B), Yb(B), a1((size_t)B * HD), a2((size_t)B * HD), gb(B), dout(B),
@@ -188,15 +210,38 @@ void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* ta
   float* gb3 = gw3 + HD;
   const float* W2 = w.p + NF * HD + HD;
 
-  auto loss_all = [&]() {
+  std::mt19937_64 rng(seed);
+  std::vector<int> uperm((size_t)nunit);
+  std::iota(uperm.begin(), uperm.end(), 0);
+  std::shuffle(uperm.begin(), uperm.end(), rng);
+  std::vector<char> is_val((size_t)nunit, 0);
+  for (int64_t u = ntr; u < nunit; ++u) is_val[uperm[u]] = 1;
+
+  // loss over the held-out units (val) or all units, from one forward pass
+  std::vector<float> hg((size_t)n);
+  auto eval = [&](bool val_only) {
     k_mlp_train_fwd(w.p, F.p, n, nullptr, nullptr, g.p, stream);
-    k_sqerr(g.p, Dv.p, Y.p, n, sq.p, stream);
-    k_sum_f(sq.p, n, one.p, stream);
-    float s = 0;
-    dev_d2h(&s, one.p, sizeof(float), stream);
-    return (double)s / (double)n;
+    dev_d2h(hg.data(), g.p, sizeof(float) * (size_t)n, stream);
+    double tot = 0;
+    int64_t cnt = 0;
+    for (int64_t u = 0; u < nunit; ++u) {
+      if (val_only && !is_val[u]) continue;
+      double A = 0, T = 0, Yy = 0, se = 0;
+      for (int64_t i = u * usz; i < (u + 1) * usz; ++i) {
+        const double t = (double)hg[i] * dcorr[i];
+        A += t * target[i];
+        T += t * t;
+        Yy += (double)target[i] * target[i];
+        se += (t - target[i]) * (t - target[i]);
+      }
+      tot += cosl ? 1.0 - A * A / ((T + 1e-300) * (Yy + 1e-300)) : se;
+      cnt += cosl ? 1 : usz;
+    }
+    return tot / (double)std::max<int64_t>(1, cnt);
   };
-  if (loss_before) *loss_before = loss_all();
+  if (loss_before) *loss_before = eval(false);
+  std::vector<float> best(weights, weights + nw);
+  double best_val = eval(true);
 
   // the three training GEMMs on the grouped FP32 kernel (ids >= 2 only)
   DevTable tab;
@@ -213,22 +258,30 @@ void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* ta
   gW1l.add(make_contrib(B, GF_TRANS_A, i_Fb, 0, NF, i_da1, 0, HD, 1.0));
   gW1l.end();
 
-  std::mt19937_64 rng(seed);
-  std::vector<int> perm((size_t)n);
-  std::iota(perm.begin(), perm.end(), 0);
-  int* dperm = (int*)dev_alloc(sizeof(int) * (size_t)n);
+  // rows of each step: a contiguous group, or a shuffled minibatch of pairs
+  std::vector<int> rows((size_t)n);
+  int* drows = (int*)dev_alloc(sizeof(int) * (size_t)n);
   const float b1 = 0.9f, b2 = 0.999f;
   int64_t step = 0;
   try {
     for (int ep = 0; ep < epochs; ++ep) {
-      std::shuffle(perm.begin(), perm.end(), rng);
-      dev_h2d(dperm, perm.data(), sizeof(int) * (size_t)n);
-      for (int64_t s0 = 0; s0 + B <= n; s0 += B) {
-        k_gather_rows(F.p, dperm + s0, B, NF, Fb.p, stream);
-        k_gather_rows(Dv.p, dperm + s0, B, 1, Db.p, stream);
-        k_gather_rows(Y.p, dperm + s0, B, 1, Yb.p, stream);
+      std::vector<int> tr;
+      for (int64_t u = 0; u < nunit; ++u)
+        if (!is_val[u]) tr.push_back((int)u);
+      std::shuffle(tr.begin(), tr.end(), rng);
+      int64_t nr = 0;
+      for (int u : tr)
+        for (int64_t i = 0; i < usz; ++i) rows[nr++] = (int)(u * usz + i);
+      dev_h2d(drows, rows.data(), sizeof(int) * (size_t)nr);
+      for (int64_t s0 = 0; s0 + B <= nr; s0 += B) {
+        k_gather_rows(F.p, drows + s0, B, NF, Fb.p, stream);
+        k_gather_rows(Dv.p, drows + s0, B, 1, Db.p, stream);
+        k_gather_rows(Y.p, drows + s0, B, 1, Yb.p, stream);
         k_mlp_train_fwd(w.p, Fb.p, B, a1.p, a2.p, gb.p, stream);
-        k_mlp_bwd_out(w.p, gb.p, Db.p, Yb.p, a2.p, B, dout.p, dz2.p, stream);
+        if (cosl)
+          k_mlp_cos_grad(w.p, gb.p, Db.p, Yb.p, a2.p, B, dout.p, dz2.p, sq.p, stream);
+        else
+          k_mlp_bwd_out(w.p, gb.p, Db.p, Yb.p, a2.p, B, dout.p, dz2.p, stream);
         k_colsum(a2.p, dout.p, B, HD, gw3, stream);
         k_sum_f(dout.p, B, gb3, stream);
         k_colsum(dz2.p, nullptr, B, HD, gb2, stream);
@@ -241,15 +294,21 @@ void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* ta
         const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
         k_adam(w.p, grad.p, m.p, v.p, nw, lr, b1, b2, c1, c2, 1e-8f, stream);
       }
+      const double val = eval(true);
+      if (val < best_val) {
+        best_val = val;
+        dev_d2h(best.data(), w.p, sizeof(float) * nw, stream);
+      }
     }
     dev_sync(stream);
   } catch (...) {
-    dev_free(dperm);
+    dev_free(drows);
     throw;
   }
-  dev_free(dperm);
-  if (loss_after) *loss_after = loss_all();
-  dev_d2h(weights, w.p, sizeof(float) * nw, stream);
+  dev_free(drows);
+  std::copy(best.begin(), best.end(), weights);
+  dev_h2d(w.p, weights, sizeof(float) * nw);
+  if (loss_after) *loss_after = eval(false);
 }
 
 }  // namespace dmrg

@@ -140,10 +140,9 @@ __device__ void features(int64_t i, const double* r, const double* diag, double 
   const double dh = diag[i] - theta;
   const float sh = (float)scales[0], sr = (float)scales[1];
   f[0] = clampf((float)dh / sh, -8.f, 8.f);
-  f[1] = asinhf((float)(dh / 0.01)) / 8.f;
-  const float rr = (float)r[i] / sr;
-  f[2] = clampf(rr, -8.f, 8.f);
-  f[3] = asinhf(fabsf(rr)) / 4.f;
+  f[1] = asinhf((float)(dh / scales[2])) / 4.f;
+  f[2] = clampf((float)r[i] / sr, -8.f, 8.f);
+  f[3] = (float)log10(scales[2]) / 4.f;
   const float* s = stat + (int64_t)blk[i] * (NF - 4);
 #pragma unroll
   for (int j = 0; j < NF - 4; ++j) f[4 + j] = s[j];
@@ -222,6 +221,7 @@ __global__ void scales_final(const double* part, int64_t n, double* scales) {
     const double tiny = 1e-300;
     scales[0] = sqrt(s0 / (double)n) + tiny;
     scales[1] = sqrt(s1 / (double)n) + tiny;
+    scales[2] = sqrt(s1) + tiny;
   }
 }
 
@@ -267,6 +267,44 @@ __global__ void mlp_bwd_out_kernel(const float* w, const float* g, const float* 
     const int64_t b = k / HD;
     const int j = (int)(k % HD);
     const float o = 2.f * (g[b] * d[b] - y[b]) * d[b] / (float)n;
+    if (j == 0) dout[b] = o;
+    dz2[k] = a2[k] > 0.f ? o * P.w3[j] : 0.f;
+  }
+}
+
+// Direction loss of one group (the samples of one Davidson iteration):
+// L = 1 - <t,y>^2 / (<t,t> <y,y>) with t_b = g_b d_b.  One block computes the
+// three sums in a fixed order, then dL/dg_b = (dL/dt_b) d_b and
+// dz2 = dL/dg w3 [a2 > 0]; loss[0] receives L.
+__global__ void mlp_cos_grad_kernel(const float* w, const float* g, const float* d, const float* y, const float* a2,
+                                    int64_t n, float* dout, float* dz2, float* loss) {
+  __shared__ float red[3][256];
+  float A = 0.f, T = 0.f, Y = 0.f;
+  for (int64_t b = threadIdx.x; b < n; b += blockDim.x) {
+    const float t = g[b] * d[b];
+    A += t * y[b];
+    T += t * t;
+    Y += y[b] * y[b];
+  }
+  red[0][threadIdx.x] = A;
+  red[1][threadIdx.x] = T;
+  red[2][threadIdx.x] = Y;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  A = red[0][0];
+  T = red[1][0] + 1e-30f;
+  Y = red[2][0] + 1e-30f;
+  if (threadIdx.x == 0) *loss = 1.f - A * A / (T * Y);
+  const WPtr P = wptr(w);
+  for (int64_t k = threadIdx.x; k < n * HD; k += blockDim.x) {
+    const int64_t b = k / HD;
+    const int j = (int)(k % HD);
+    const float t = g[b] * d[b];
+    const float o = (-2.f * A * y[b] / (T * Y) + 2.f * A * A * t / (T * T * Y)) * d[b];
     if (j == 0) dout[b] = o;
     dz2[k] = a2[k] > 0.f ? o * P.w3[j] : 0.f;
   }
@@ -366,6 +404,12 @@ void k_mlp_bwd_out(const float* w, const float* g, const float* d, const float* 
                    float* dout, float* dz2, void* s) {
   hipLaunchKernelGGL(mlp_bwd_out_kernel, dim3(grid_for(n * HD)), dim3(256), 0, S(s), w, g, d, y, a2, n, dout, dz2);
   dev_check("k_mlp_bwd_out");
+}
+
+void k_mlp_cos_grad(const float* w, const float* g, const float* d, const float* y, const float* a2, int64_t n,
+                    float* dout, float* dz2, float* loss, void* s) {
+  hipLaunchKernelGGL(mlp_cos_grad_kernel, dim3(1), dim3(256), 0, S(s), w, g, d, y, a2, n, dout, dz2, loss);
+  dev_check("k_mlp_cos_grad");
 }
 
 void k_relu_mask(float* dz, const float* a, int64_t n, void* s) {

@@ -86,7 +86,7 @@ struct Ops {
 };
 
 struct BuildOptions {
-  size_t x_budget = size_t(4) << 30;       // bytes of R-step scratch
+  size_t x_budget = size_t(16) << 30;      // bytes of each R-step scratch slot (fewer, longer launches)
   size_t t_budget = size_t(2) << 30;       // bytes of renormalization scratch
 };
 
@@ -110,9 +110,11 @@ void diag_run(Ops& ops, double* diag, void* stream);
 void make_reduced_copies(Ops& ops, void* stream);
 
 // Called by Davidson every iteration with the Ritz vector x, residual r,
-// diag(H) and the Ritz value (device scalar), before the correction step.
+// diag(H), the Ritz value (device scalar) and the current subspace (m
+// orthonormal vectors of n_psi elements, V[j * n_psi + i]), before the
+// correction step.
 using DavidsonHook = std::function<void(const double* x, const double* r, const double* diag,
-                                        const double* theta_dev, int iter)>;
+                                        const double* theta_dev, const double* V, int m, int iter)>;
 int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* energy, dmrg_davidson_stats* st,
                  void* stream, const DavidsonHook& hook = DavidsonHook());
 
@@ -126,7 +128,8 @@ void mlp_apply_once(Ops& O, const float* weights, const double* r, const double*
                     void* stream);
 int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_iter, int per_iter, uint64_t seed,
                     int64_t cap, float* feat, float* dcorr, float* target, void* stream);
-void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* target, int epochs, int batch,
-               float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after, void* stream);
+void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* target, int group, int epochs,
+               int batch, float lr, uint64_t seed, float* weights, double* loss_before, double* loss_after,
+               void* stream);
 
 }  // namespace dmrg

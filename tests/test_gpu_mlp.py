@@ -38,9 +38,10 @@ def np_features(ops, mps, r, dg, theta):
     sr = np.sqrt(np.mean(r * r)) + 1e-300
     F = np.zeros((len(r), NF))
     F[:, 0] = np.clip(dh / sh, -8, 8)
-    F[:, 1] = np.arcsinh(dh / 0.01) / 8
+    rn = np.linalg.norm(r) + 1e-300
+    F[:, 1] = np.arcsinh(dh / rn) / 4
     F[:, 2] = np.clip(r / sr, -8, 8)
-    F[:, 3] = np.arcsinh(np.abs(r) / sr) / 4
+    F[:, 3] = np.log10(rn) / 4
     secL, secR = mps.sectors[k], mps.sectors[k + 2]
     rK = np.sqrt(K)
     for b, (il, n1, n2, ir, dl, dr) in enumerate(ops.blk_meta):
@@ -145,6 +146,14 @@ def test_mlp_collect_and_train_reduce_loss(ctx):
     print(f"loss before {lb:.4e} (numpy {ref_lb:.4e}) after {la:.4e}")
     assert abs(lb - ref_lb) <= 1e-3 * ref_lb
     assert la < lb
+    # direction loss per Davidson iteration (groups of 512 samples)
+    w = B.mlp_init(ctx.lib, 5)
+    lb, la = B.mlp_train(ctx, feat, dc, tg, w, epochs=4, lr=1e-3, seed=1, group=512)
+    d64, t64 = dc.astype(np.float64).reshape(-1, 512), tg.astype(np.float64).reshape(-1, 512)
+    ref_lb = float(np.mean(1 - (d64 * t64).sum(1) ** 2 / ((d64 ** 2).sum(1) * (t64 ** 2).sum(1))))
+    print(f"direction loss before {lb:.4e} (numpy {ref_lb:.4e}) after {la:.4e}")
+    assert abs(lb - ref_lb) <= 1e-4 + 1e-3 * ref_lb
+    assert la <= lb
 
 
 def test_davidson_with_mlp_reaches_fci(ctx):
