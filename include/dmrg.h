@@ -201,12 +201,22 @@ int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops,
                        const double* const* psi, double* const* sigma, int precision, int flags);
 
 /* Autotune the launch shapes of dmrg_sigma in one precision: every tile shape
- * (64x64, 32x32, 64x32, 32x64 outputs per workgroup) and then a persistent
+ * (64x64, 32x32, 64x32, 32x64 outputs per workgroup, and the mixed shape of
+ * dmrg_launch_shape) and then a persistent
  * grid are timed per launch on one sigma call each, and the fastest is kept
  * for later calls (results do not change).  Synchronous.  ms_default /
  * ms_tuned (may be NULL) receive the summed launch times with the default
  * and the chosen shapes. */
 int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_default, double* ms_tuned);
+
+/* Launch shapes of dmrg_sigma in one precision, set by hand (what the
+ * autotuner otherwise chooses): tile 0 = 64x64, 1 = 32x32, 2 = 64x32,
+ * 3 = 32x64 outputs per workgroup, 4 = mixed (64x64 interior, 32-wide strips
+ * for at most 32 rows or columns left over, per task); grid_per_xcd > 0 caps
+ * the workgroups per XCD (persistent), 0 = one per job.  Results do not
+ * depend on the shape.  The task lists for a new shape are built on first
+ * use (synchronous). */
+int dmrg_launch_shape(dmrg_ops* ops, int precision, int tile, int64_t grid_per_xcd);
 
 /* Lowest eigenpair.  psi (device, n_psi) holds the initial guess and receives
  * the normalised eigenvector; *energy its FP64 Rayleigh quotient (ecore

@@ -21,7 +21,8 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ESHAPE", -3: "DMRG_ENOMEM",
 EXPORTS = ["dmrg_create", "dmrg_destroy", "dmrg_last_error", "dmrg_build_ops", "dmrg_ops_destroy",
            "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_sigma_batched",
            "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile", "dmrg_mlp_nweights",
-           "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply", "dmrg_autotune"]
+           "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply", "dmrg_autotune",
+           "dmrg_launch_shape"]
 MLP_NFEAT, MLP_HIDDEN = 18, 256
 
 
@@ -88,6 +89,7 @@ def load(path=None):
     lib.dmrg_diag.argtypes = [vp, vp, vp]
     lib.dmrg_sigma_batched.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_int]
     lib.dmrg_autotune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.dmrg_launch_shape.argtypes = [vp, C.c_int, C.c_int, C.c_int64]
     lib.dmrg_davidson.argtypes = [vp, vp, vp, C.POINTER(DavidsonOpts), C.POINTER(C.c_double),
                                   C.POINTER(DavidsonStats)]
     lib.dmrg_davidson_default_opts.argtypes = [C.POINTER(DavidsonOpts)]
@@ -186,6 +188,10 @@ class Ops:
         a, b = C.c_double(), C.c_double()
         self.ctx._check(self.ctx.lib.dmrg_autotune(self.ctx.h, self.h, int(precision), C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def launch_shape(self, precision, tile, grid_per_xcd=0):
+        """Force the launch shape of dmrg_sigma in one precision (see dmrg.h)."""
+        self.ctx._check(self.ctx.lib.dmrg_launch_shape(self.h, int(precision), int(tile), int(grid_per_xcd)))
 
     def profile(self, enable=True):
         self.ctx._check(self.ctx.lib.dmrg_profile(self.h, int(enable)))

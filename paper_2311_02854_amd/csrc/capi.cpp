@@ -200,6 +200,19 @@ int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops, con
   });
 }
 
+int dmrg_launch_shape(dmrg_ops* ops, int precision, int tile, int64_t grid_per_xcd) {
+  if (!ops || precision < 0 || precision > 2 || tile < 0 || tile >= dmrg::NTILE || grid_per_xcd < 0)
+    return DMRG_EINVAL;
+  try {
+    dmrg::Ops& O = *ops->p;
+    O.tile_choice[precision].assign(O.launches.size(), tile);
+    O.grid_choice[precision].assign(O.launches.size(), grid_per_xcd);
+    return DMRG_OK;
+  } catch (...) {
+    return DMRG_EINTERNAL;
+  }
+}
+
 int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_default, double* ms_tuned) {
   if (!ctx || !ops) return DMRG_EINVAL;
   return guarded(ctx, [&] {

@@ -20,6 +20,8 @@ struct GTask {
   int32_t c_buf;
   int32_t ldc;
   int32_t accumulate;
+  int32_t shape;      // tile shape of this task in a mixed-shape launch (TILE_*)
+  int32_t pad_;
   int64_t c_off, c_bstride;
   int32_t contrib_begin, contrib_end;
   int64_t job_begin;  // first job of this piece in its XCD's job numbering
@@ -46,7 +48,10 @@ enum : int32_t { GT_ACCUM = 1, GT_C64 = 2 };
 // Workgroup tile shapes of the grouped GEMM (rows x columns of C)
 // (larger tiles, 64x128 up to 128x128, were measured slower on this GPU:
 // their register tiles drop the occupancy to 1-2 waves per SIMD)
-enum : int { TILE_64x64 = 0, TILE_32x32 = 1, TILE_64x32 = 2, TILE_32x64 = 3, NTILE = 4 };
+// TILE_EDGE: every task is cut into its 64x64-tiled interior and, where the
+// rows or columns left over number at most 32, a 32x64 bottom strip, a 64x32
+// right strip and a 32x32 corner, all in one launch (per-task shape).
+enum : int { TILE_64x64 = 0, TILE_32x32 = 1, TILE_64x32 = 2, TILE_32x64 = 3, TILE_EDGE = 4, NTILE = 5 };
 inline int tile_rows(int t) { return (t == TILE_32x32 || t == TILE_32x64) ? 32 : 64; }
 inline int tile_cols(int t) { return (t == TILE_32x32 || t == TILE_64x32) ? 32 : 64; }
 

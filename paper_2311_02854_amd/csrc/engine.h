@@ -132,6 +132,7 @@ class GemmList {
   // Estimated MFMA work of one job of task t at tile shape `tl` (k steps x
   // active 16x16 sub-tiles of the workgroup).
   static double job_cost(const GTask& t, const GContrib* cs, int tl) {
+    if (tl == TILE_EDGE) tl = TILE_64x64;
     const int tr = tile_rows(tl), tc = tile_cols(tl);
     const int am = t.M < tr ? t.M : tr, an = t.N < tc ? t.N : tc;
     const double sub = double((am + 15) / 16) * ((an + 15) / 16);
@@ -143,6 +144,7 @@ class GemmList {
     return c;
   }
   static int64_t jobs_at(const GTask& t, int tl) {
+    if (tl == TILE_EDGE) tl = TILE_64x64;
     return (int64_t)((t.M + tile_rows(tl) - 1) / tile_rows(tl)) * ((t.N + tile_cols(tl) - 1) / tile_cols(tl)) *
            t.nbatch;
   }
@@ -179,26 +181,79 @@ class GemmList {
     return m;
   }
 
+  // Split every task for TILE_EDGE: the interior (rows and columns in whole
+  // 64-tiles, plus a last partial 64-tile when more than 32 of it are used)
+  // with 64x64 tiles, the rows left over (at most 32) with 32x64 tiles, the
+  // columns left over with 64x32 tiles and the corner with 32x32 tiles.  The
+  // regions write disjoint parts of C; each carries the task's contributions
+  // with the operand offsets moved to its first row and column.
+  void split_edges(std::vector<GTask>& out, std::vector<GContrib>& cx) const {
+    for (const GTask& t : tasks) {
+      const int rm = t.M % 64, rn = t.N % 64;
+      const int Mi = (rm > 0 && rm <= 32) ? t.M - rm : t.M, Ni = (rn > 0 && rn <= 32) ? t.N - rn : t.N;
+      const int reg[4][5] = {{0, 0, Mi, Ni, TILE_64x64},
+                             {Mi, 0, t.M - Mi, Ni, TILE_32x64},
+                             {0, Ni, Mi, t.N - Ni, TILE_64x32},
+                             {Mi, Ni, t.M - Mi, t.N - Ni, TILE_32x32}};
+      for (const auto& r : reg) {
+        const int m0 = r[0], n0 = r[1], M = r[2], N = r[3];
+        if (M <= 0 || N <= 0) continue;
+        GTask g = t;
+        g.M = M;
+        g.N = N;
+        g.shape = r[4];
+        g.c_off = t.c_off + (int64_t)m0 * t.ldc + n0;
+        g.contrib_begin = (int32_t)cx.size();
+        for (int i = t.contrib_begin; i < t.contrib_end; ++i) {
+          GContrib c = contribs[i];
+          const bool ta = c.flags & GF_TRANS_A, tb = c.flags & GF_TRANS_B;
+          if (c.flags & GF_IDENT_A) {
+            c.b_off += tb ? (int64_t)n0 * c.ldb + m0 : (int64_t)m0 * c.ldb + n0;
+          } else {
+            c.a_off += ta ? (int64_t)m0 : (int64_t)m0 * c.lda;
+            c.b_off += tb ? (int64_t)n0 * c.ldb : (int64_t)n0;
+          }
+          cx.push_back(c);
+        }
+        g.contrib_end = (int32_t)cx.size();
+        out.push_back(g);
+      }
+    }
+  }
+
   // Count tiles for shape tl, split tasks into job-range pieces, assign them
   // to XCDs (longest processing time first) and upload the per-XCD lists.
   void upload(int tl) {
     DMRG_CHECK(tl >= 0 && tl < NTILE, DMRG_EINVAL, "unknown tile shape");
     free_dev(dev_[tl]);
     if (tasks.empty()) return;
-    if (!dcontribs_) {
-      dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
-      if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
-      ncontribs_dev_ = contribs.size();
-    }
     Dev& D = dev_[tl];
+    std::vector<GTask> src;
+    std::vector<GContrib> cx;
+    const GContrib* cs = contribs.data();
+    if (tl == TILE_EDGE) {
+      split_edges(src, cx);
+      cs = cx.data();
+      D.contribs = (GContrib*)dev_alloc((cx.size() + 1) * sizeof(GContrib));
+      if (!cx.empty()) dev_h2d(D.contribs, cx.data(), cx.size() * sizeof(GContrib));
+      D.ncontribs = cx.size();
+    } else {
+      src = tasks;
+      for (GTask& g : src) g.shape = tl;
+      if (!dcontribs_) {
+        dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
+        if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
+        ncontribs_dev_ = contribs.size();
+      }
+    }
     std::memset(&D.map, 0, sizeof(D.map));
     std::vector<GTask> dev;
-    std::vector<double> cj(tasks.size());
-    std::vector<int64_t> nj(tasks.size());
+    std::vector<double> cj(src.size());
+    std::vector<int64_t> nj(src.size());
     double total = 0;
-    for (size_t t = 0; t < tasks.size(); ++t) {
-      cj[t] = job_cost(tasks[t], contribs.data(), tl);
-      nj[t] = jobs_at(tasks[t], tl);
+    for (size_t t = 0; t < src.size(); ++t) {
+      cj[t] = job_cost(src[t], cs, src[t].shape);
+      nj[t] = jobs_at(src[t], src[t].shape);
       total += cj[t] * nj[t];
     }
     const double piece_cost = std::max(total / (NXCD * 32.0), 1.0);
@@ -208,7 +263,7 @@ class GemmList {
       double c;
     };
     std::vector<Piece> pcs;
-    for (size_t t = 0; t < tasks.size(); ++t) {
+    for (size_t t = 0; t < src.size(); ++t) {
       int64_t np = (int64_t)std::ceil(cj[t] * nj[t] / piece_cost);
       np = std::max<int64_t>(1, std::min<int64_t>(np, nj[t]));
       for (int64_t i = 0; i < np; ++i) {
@@ -232,9 +287,9 @@ class GemmList {
       D.map.task_begin[x] = (int)dev.size();
       int64_t jb = 0;
       for (const Piece& p : per[x]) {
-        GTask g = tasks[p.t];
-        g.tiles_m = (g.M + tile_rows(tl) - 1) / tile_rows(tl);
-        g.tiles_n = (g.N + tile_cols(tl) - 1) / tile_cols(tl);
+        GTask g = src[p.t];
+        g.tiles_m = (g.M + tile_rows(g.shape) - 1) / tile_rows(g.shape);
+        g.tiles_n = (g.N + tile_cols(g.shape) - 1) / tile_cols(g.shape);
         g.job_begin = jb;
         g.job_off = p.off;
         g.njob = p.n;
@@ -273,8 +328,8 @@ class GemmList {
     if (!dev_[tl].tasks) upload(tl);
     const Dev& D = dev_[tl];
     if (D.ntasks == 0) return;
-    gemm_launch(D.tasks, D.ntasks, D.map, dcontribs_, D.bucket, tab.device(), p0, p1, elem, tl, grid_per_xcd,
-                stream);
+    gemm_launch(D.tasks, D.ntasks, D.map, D.contribs ? D.contribs : dcontribs_, D.bucket, tab.device(), p0, p1,
+                elem, tl, grid_per_xcd, stream);
   }
   void release() {
     for (int t = 0; t < NTILE; ++t) free_dev(dev_[t]);
@@ -293,7 +348,7 @@ class GemmList {
   size_t host_bytes() const { return tasks.size() * sizeof(GTask) + contribs.size() * sizeof(GContrib); }
   size_t device_bytes() const {
     size_t b = ncontribs_dev_ * sizeof(GContrib);
-    for (int t = 0; t < NTILE; ++t) b += (size_t)dev_[t].ntasks * sizeof(GTask);
+    for (int t = 0; t < NTILE; ++t) b += (size_t)dev_[t].ntasks * sizeof(GTask) + dev_[t].ncontribs * sizeof(GContrib);
     return b;
   }
 
@@ -301,12 +356,15 @@ class GemmList {
   struct Dev {
     GTask* tasks = nullptr;
     int* bucket = nullptr;
+    GContrib* contribs = nullptr;  // own contribution array (TILE_EDGE), else the shared one
+    size_t ncontribs = 0;
     XcdMap map{};
     int ntasks = 0;
   };
   static void free_dev(Dev& d) {
     dev_free(d.tasks);
     dev_free(d.bucket);
+    dev_free(d.contribs);
     d = Dev{};
   }
   bool any_dev() const {

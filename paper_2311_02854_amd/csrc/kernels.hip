@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cstdio>
 #include <string>
+#include <type_traits>
 
 #include "../../include/dmrg.h"
 #include "common.h"
@@ -336,28 +337,23 @@ struct Step {
   int K;
 };
 
-// Grouped GEMM over a task list (see device.h).  Operand buffers hold P::T;
-// the output is P::T, or binary64 for tasks flagged GT_C64 (buffer 1 is p1).
+// One job of a grouped GEMM task: the tile `local` (batch-major) of task Tk
+// with a (32 WM) x (32 WN) workgroup tile.  smem holds at least
+// sizeof(Smem<P, 32 WM, 32 WN>) bytes.
 template <class P, int WM, int WN>
-__global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ tasks, const XcdMap map,
-                                                  const GContrib* __restrict__ contribs,
-                                                  const int* __restrict__ bucket_all,
-                                                  typename P::T* const* __restrict__ table,
-                                                  const typename P::T* p0, double* p1) {
+__device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* smem,
+                                         const GContrib* __restrict__ contribs,
+                                         typename P::T* const* __restrict__ table, const typename P::T* p0,
+                                         double* p1) {
   using T = typename P::T;
   using Acc = typename P::Acc;
   constexpr int BM = 32 * WM, BN = 32 * WN, EA = BM * BK / NT, EB = BN * BK / NT;
-  __shared__ Smem<P, BM, BN> sm;
+  Smem<P, BM, BN>& sm = *reinterpret_cast<Smem<P, BM, BN>*>(smem);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
   const int lr = lane & 15, lk = lane >> 4;
-  const int xcd = blockIdx.x % NXCD;
-  const int64_t njobs = map.njobs[xcd];
-  const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
   auto opp = [&](int id) -> const T* { return id == 0 ? p0 : (id == 1 ? (const T*)p1 : table[id]); };
-  for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) {
-    const GTask Tk = tasks[find_task(tasks, bucket, map.shift, job)];
-    const int64_t local = job - Tk.job_begin + Tk.job_off;
+  {
     const int tiles = Tk.tiles_m * Tk.tiles_n;
     const int64_t batch = local / tiles;
     const int tile = (int)(local - batch * tiles);
@@ -559,22 +555,63 @@ __global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ t
   }
 }
 
+// Grouped GEMM over a task list (see device.h).  Operand buffers hold P::T;
+// the output is P::T, or binary64 for tasks flagged GT_C64 (buffer 1 is p1).
+// MIXED: every task carries its own tile shape (TILE_EDGE launches).
+template <class P, int WM, int WN, bool MIXED>
+__global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ tasks, const XcdMap map,
+                                                  const GContrib* __restrict__ contribs,
+                                                  const int* __restrict__ bucket_all,
+                                                  typename P::T* const* __restrict__ table,
+                                                  const typename P::T* p0, double* p1) {
+  using SmemT = std::conditional_t<MIXED, Smem<P, 64, 64>, Smem<P, 32 * WM, 32 * WN>>;
+  __shared__ SmemT smem;
+  const int xcd = blockIdx.x % NXCD;
+  const int64_t njobs = map.njobs[xcd];
+  const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
+  for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) {
+    const GTask Tk = tasks[find_task(tasks, bucket, map.shift, job)];
+    const int64_t local = job - Tk.job_begin + Tk.job_off;
+    if constexpr (!MIXED) {
+      gemm_job<P, WM, WN>(Tk, local, &smem, contribs, table, p0, p1);
+    } else {
+      switch (Tk.shape) {
+        case TILE_32x64:
+          gemm_job<P, 1, 2>(Tk, local, &smem, contribs, table, p0, p1);
+          break;
+        case TILE_64x32:
+          gemm_job<P, 2, 1>(Tk, local, &smem, contribs, table, p0, p1);
+          break;
+        case TILE_32x32:
+          gemm_job<P, 1, 1>(Tk, local, &smem, contribs, table, p0, p1);
+          break;
+        default:
+          gemm_job<P, 2, 2>(Tk, local, &smem, contribs, table, p0, p1);
+          break;
+      }
+    }
+  }
+}
+
 template <class P>
 static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, const XcdMap& map,
                            const GContrib* c, const int* bk, typename P::T* const* tab, const typename P::T* p0,
                            double* p1) {
   switch (tile) {
     case TILE_64x64:
-      hipLaunchKernelGGL((gemm_kernel<P, 2, 2>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      hipLaunchKernelGGL((gemm_kernel<P, 2, 2, false>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
       break;
     case TILE_32x32:
-      hipLaunchKernelGGL((gemm_kernel<P, 1, 1>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      hipLaunchKernelGGL((gemm_kernel<P, 1, 1, false>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
       break;
     case TILE_64x32:
-      hipLaunchKernelGGL((gemm_kernel<P, 2, 1>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      hipLaunchKernelGGL((gemm_kernel<P, 2, 1, false>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
       break;
     case TILE_32x64:
-      hipLaunchKernelGGL((gemm_kernel<P, 1, 2>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      hipLaunchKernelGGL((gemm_kernel<P, 1, 2, false>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      break;
+    case TILE_EDGE:
+      hipLaunchKernelGGL((gemm_kernel<P, 2, 2, true>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
       break;
 
     default:

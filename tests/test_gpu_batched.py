@@ -96,6 +96,19 @@ def test_batched_new_output_buffers(ctx, probs):
         assert np.array_equal(u, v)
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_every_launch_shape_gives_identical_sigma(ctx, probs, prec):
+    # 64x64, 32x32, 64x32, 32x64, mixed edge strips; one workgroup per job and persistent
+    ints, mps, ops, x = probs[2]
+    ref = single(ops, x, prec)
+    for tile in range(5):
+        for grid in (0, 64):
+            ops.launch_shape(prec, tile, grid)
+            got = single(ops, x, prec)
+            assert np.array_equal(got, ref), (tile, grid, np.abs(got - ref).max())
+    ops.launch_shape(prec, 0, 0)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_autotune_single_keeps_results(ctx, probs, prec):
     ints, mps, ops, x = probs[4]
