@@ -202,8 +202,8 @@ int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops,
 
 /* Autotune the launch shapes of dmrg_sigma in one precision: every tile shape
  * (64x64, 32x32, 64x32, 32x64 outputs per workgroup, and the mixed shape of
- * dmrg_launch_shape) and then a persistent
- * grid are timed per launch on one sigma call each, and the fastest is kept
+ * dmrg_launch_shape), each with one workgroup per job and with dynamic units
+ * (grid_per_xcd -1), is timed per launch on one sigma call, and the fastest is kept
  * for later calls (results do not change).  Synchronous.  ms_default /
  * ms_tuned (may be NULL) receive the summed launch times with the default
  * and the chosen shapes. */
@@ -213,8 +213,10 @@ int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_defaul
  * autotuner otherwise chooses): tile 0 = 64x64, 1 = 32x32, 2 = 64x32,
  * 3 = 32x64 outputs per workgroup, 4 = mixed (64x64 interior, 32-wide strips
  * for at most 32 rows or columns left over, per task); grid_per_xcd > 0 caps
- * the workgroups per XCD (persistent), 0 = one per job.  Results do not
- * depend on the shape.  The task lists for a new shape are built on first
+ * the workgroups per XCD (persistent, jobs dealt round robin), 0 = one
+ * workgroup per job, -1 = dynamic: the workgroups that fit on the chip at
+ * once take cost-balanced ranges of jobs from a per-XCD counter.  Other
+ * negative values are DMRG_EINVAL.  Results do not depend on the shape.  The task lists for a new shape are built on first
  * use (synchronous). */
 int dmrg_launch_shape(dmrg_ops* ops, int precision, int tile, int64_t grid_per_xcd);
 

@@ -201,7 +201,7 @@ int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops, con
 }
 
 int dmrg_launch_shape(dmrg_ops* ops, int precision, int tile, int64_t grid_per_xcd) {
-  if (!ops || precision < 0 || precision > 2 || tile < 0 || tile >= dmrg::NTILE || grid_per_xcd < 0)
+  if (!ops || precision < 0 || precision > 2 || tile < 0 || tile >= dmrg::NTILE || grid_per_xcd < -1)
     return DMRG_EINVAL;
   try {
     dmrg::Ops& O = *ops->p;

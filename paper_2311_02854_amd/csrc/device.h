@@ -39,6 +39,15 @@ struct XcdMap {
   int64_t njobs[NXCD];
   int64_t max_jobs;
   int32_t shift;                   // jobs per bucket = 2^shift
+  int32_t dynamic;                 // set per launch: resident workgroups take units from a counter
+  // Dynamic launches: the jobs of XCD x are cut into nunits[x] units of
+  // consecutive jobs; unit u spans jobs [units[unit_begin[x] + u],
+  // units[unit_begin[x] + u + 1]).  counters[64 x] counts the units taken
+  // on XCD x (zeroed before every launch).
+  const int64_t* units;
+  unsigned* counters;
+  int64_t unit_begin[NXCD];
+  int64_t nunits[NXCD];
 };
 
 enum : int32_t { GF_TRANS_A = 1, GF_TRANS_B = 2, GF_IDENT_A = 4 };
@@ -98,7 +107,10 @@ void graph_destroy(void* exec);
 // or P_BF16X3 (float operand buffers, split-bf16 MFMA, FP32 accumulation);
 // outputs of tasks flagged GT_C64 are double in every mode.  tile: TILE_*,
 // the shape the tasks' tiles_m / tiles_n were counted with.  grid_per_xcd > 0
-// caps the workgroups per XCD (persistent launch), else one per job.
+// caps the workgroups per XCD (persistent launch, jobs dealt round robin);
+// grid_per_xcd < 0 launches the workgroups that fit on the chip at once and
+// they take the units of map (cost-balanced job ranges) from a per-XCD
+// counter; 0 launches one workgroup per job.
 // bucket_dev[bucket_begin[x] + b] is the task of XCD x holding its job b << shift
 // (clamped to the XCD's last task); it bounds the kernel's job -> task search.
 void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,

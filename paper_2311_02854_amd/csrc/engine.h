@@ -58,7 +58,7 @@ class DevTable {
 class GemmList {
  public:
   int tile = TILE_64x64;       // shape used by run()
-  int64_t grid_per_xcd = 0;    // > 0: persistent launch with this many workgroups per XCD
+  int64_t grid_per_xcd = 0;    // > 0: persistent launch with this many workgroups per XCD; < 0: dynamic units
   std::vector<GTask> tasks;
   std::vector<GContrib> contribs;
   int64_t njobs = 0;           // jobs at 64x64 tiles (for reporting)
@@ -281,12 +281,26 @@ class GemmList {
       load[x] += p.c * p.n;
       per[x].push_back(p);
     }
+    // Units for dynamic launches (guided self-scheduling): a unit of
+    // consecutive jobs takes about 1/(4 S) of the work left on its XCD, with
+    // S = 128 workgroups per XCD, and at least one job.
+    std::vector<int64_t> units;
     for (int x = 0; x < NXCD; ++x) {
       // longest jobs first inside an XCD
       std::stable_sort(per[x].begin(), per[x].end(), [](const Piece& a, const Piece& b) { return a.c > b.c; });
       D.map.task_begin[x] = (int)dev.size();
+      D.map.unit_begin[x] = (int64_t)units.size();
+      double rem = load[x];
       int64_t jb = 0;
       for (const Piece& p : per[x]) {
+        for (int64_t left = p.n, j = jb; left > 0;) {
+          const double target = std::max(p.c, rem / (4.0 * 128));
+          const int64_t g = std::max<int64_t>(1, std::min<int64_t>(left, (int64_t)(target / p.c)));
+          units.push_back(j);
+          j += g;
+          left -= g;
+          rem -= p.c * g;
+        }
         GTask g = src[p.t];
         g.tiles_m = (g.M + tile_rows(g.shape) - 1) / tile_rows(g.shape);
         g.tiles_n = (g.N + tile_cols(g.shape) - 1) / tile_cols(g.shape);
@@ -298,7 +312,14 @@ class GemmList {
       }
       D.map.njobs[x] = jb;
       D.map.max_jobs = std::max(D.map.max_jobs, jb);
+      units.push_back(jb);
+      D.map.nunits[x] = (int64_t)units.size() - 1 - D.map.unit_begin[x];
     }
+    D.units = (int64_t*)dev_alloc(units.size() * sizeof(int64_t));
+    dev_h2d(D.units, units.data(), units.size() * sizeof(int64_t));
+    D.counters = (unsigned*)dev_alloc(64 * NXCD * sizeof(unsigned));
+    D.map.units = D.units;
+    D.map.counters = D.counters;
     D.map.task_begin[NXCD] = (int)dev.size();
     D.map.shift = 0;
     while ((D.map.max_jobs >> D.map.shift) > (int64_t(1) << 14)) ++D.map.shift;
@@ -357,6 +378,8 @@ class GemmList {
     GTask* tasks = nullptr;
     int* bucket = nullptr;
     GContrib* contribs = nullptr;  // own contribution array (TILE_EDGE), else the shared one
+    int64_t* units = nullptr;      // unit boundaries of dynamic launches
+    unsigned* counters = nullptr;  // per-XCD unit counters of dynamic launches
     size_t ncontribs = 0;
     XcdMap map{};
     int ntasks = 0;
@@ -365,6 +388,8 @@ class GemmList {
     dev_free(d.tasks);
     dev_free(d.bucket);
     dev_free(d.contribs);
+    dev_free(d.units);
+    dev_free(d.counters);
     d = Dev{};
   }
   bool any_dev() const {

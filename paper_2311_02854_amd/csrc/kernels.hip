@@ -126,6 +126,7 @@ struct PolF64 {
   using T = double;
   using Acc = d4_t;
   static constexpr bool split = false;
+  static constexpr int depth = 1;  // k tiles in flight in registers
   static constexpr int PAD = 2;
   static constexpr int RL = 1, RV = 4;  // result row of element v in lane l: RL*(l/16) + RV*v
 };
@@ -133,6 +134,7 @@ struct PolF32 {
   using T = float;
   using Acc = f4_t;
   static constexpr bool split = false;
+  static constexpr int depth = 1;
   static constexpr int PAD = 4;
   static constexpr int RL = 4, RV = 1;
 };
@@ -140,6 +142,7 @@ struct PolBF3 {
   using T = float;
   using Acc = f4_t;
   static constexpr bool split = true;
+  static constexpr int depth = 2;
   static constexpr int PAD = 8;
   static constexpr int RL = 4, RV = 1;
 };
@@ -251,25 +254,43 @@ __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, i
   o.scale = scale;
 }
 
-// Out-of-range elements load from the operand's origin (always valid) and
-// are zeroed by a select, so the loads issue back to back without branches;
-// nothing consumes them until the next LDS store.
+// Out-of-range elements load from a page of zeros, so a tile needs no mask
+// between its loads and its LDS store: the loads issue back to back without
+// branches, and a register set can wait in flight while another is staged.
+__device__ const double g_zero_page[2] = {0.0, 0.0};
+template <typename T>
+__device__ __forceinline__ const T* zero_page() {
+  return reinterpret_cast<const T*>(g_zero_page);
+}
+
 template <int E, typename T>
-__device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E], bool (&ok)[E]) {
+__device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E]) {
   const T* p = o.base + (int64_t)(k0 / BK) * o.step_k;
 #pragma unroll
   for (int it = 0; it < E; ++it) {
     const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
-    ok[it] = (r < o.rows) & (k < o.K);
-    v[it] = gld(ok[it] ? p + it * o.step_it : o.origin);
+    v[it] = gld(((r < o.rows) & (k < o.K)) ? p + it * o.step_it : zero_page<T>());
   }
 }
 
-template <int E, typename T, int LD>
-__device__ __forceinline__ void opnd_store(const Opnd<T>& o, const T (&v)[E], const bool (&ok)[E], T (*L)[LD]) {
+// Element it of a thread's share of a ROWS x BK tile sits at (row, k) =
+// (r_first + it*r_inc, k_first + it*k_inc), with the pattern opnd_setup
+// picks for k-contiguous (kc) or row-contiguous operands.
+template <int ROWS>
+__device__ __forceinline__ void tile_pattern(bool kc, int& r_first, int& k_first, int& r_inc, int& k_inc) {
+  const int tid = threadIdx.x;
+  r_first = kc ? tid >> 5 : tid % ROWS;
+  k_first = kc ? tid & 31 : tid / ROWS;
+  r_inc = kc ? 8 : 0;
+  k_inc = kc ? 0 : NT / ROWS;
+}
+
+template <int ROWS, int E, typename T, int LD>
+__device__ __forceinline__ void opnd_store(bool kc, T scale, const T (&v)[E], T (*L)[LD]) {
+  int r_first, k_first, r_inc, k_inc;
+  tile_pattern<ROWS>(kc, r_first, k_first, r_inc, k_inc);
 #pragma unroll
-  for (int it = 0; it < E; ++it)
-    L[o.k_first + it * o.k_inc][o.r_first + it * o.r_inc] = ok[it] ? v[it] * o.scale : T(0);
+  for (int it = 0; it < E; ++it) L[k_first + it * k_inc][r_first + it * r_inc] = v[it] * scale;
 }
 
 // Split-BF16 staging: every thread owns E/2 pairs of k-consecutive elements
@@ -303,27 +324,36 @@ __device__ __forceinline__ void opnd_setup_split(Opnd<float>& o, const float* X,
 }
 
 template <int E>
-__device__ __forceinline__ void opnd_load_split(const Opnd<float>& o, int k0, float (&v)[E], bool (&ok)[E]) {
+__device__ __forceinline__ void opnd_load_split(const Opnd<float>& o, int k0, float (&v)[E]) {
   const float* p = o.base + (int64_t)(k0 / BK) * o.step_k;
 #pragma unroll
   for (int it = 0; it < E / 2; ++it) {
     const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
     const bool rv = r < o.rows;
-    ok[2 * it] = rv & (k < o.K);
-    ok[2 * it + 1] = rv & (k + 1 < o.K);
     const float* q = p + it * o.step_it;
-    v[2 * it] = gld(ok[2 * it] ? q : o.origin);
-    v[2 * it + 1] = gld(ok[2 * it + 1] ? q + o.s2 : o.origin);
+    v[2 * it] = gld((rv & (k < o.K)) ? q : zero_page<float>());
+    v[2 * it + 1] = gld((rv & (k + 1 < o.K)) ? q + o.s2 : zero_page<float>());
   }
 }
 
-template <int E, int LD>
-__device__ __forceinline__ void opnd_store_split(const Opnd<float>& o, const float (&v)[E], const bool (&ok)[E],
-                                                 uint16_t (*H)[LD], uint16_t (*Lo)[LD]) {
+template <int ROWS>
+__device__ __forceinline__ void tile_pattern_split(bool kc, int& r_first, int& k_first, int& r_inc, int& k_inc) {
+  const int tid = threadIdx.x;
+  r_first = kc ? tid >> 4 : tid % ROWS;
+  k_first = kc ? 2 * (tid & 15) : 2 * (tid / ROWS);
+  r_inc = kc ? NT / 16 : 0;
+  k_inc = kc ? 0 : 2 * NT / ROWS;
+}
+
+template <int ROWS, int E, int LD>
+__device__ __forceinline__ void opnd_store_split(bool kc, float scale, const float (&v)[E], uint16_t (*H)[LD],
+                                                 uint16_t (*Lo)[LD]) {
+  int r_first, k_first, r_inc, k_inc;
+  tile_pattern_split<ROWS>(kc, r_first, k_first, r_inc, k_inc);
 #pragma unroll
   for (int it = 0; it < E / 2; ++it) {
-    const int r = o.r_first + it * o.r_inc, k = o.k_first + it * o.k_inc;
-    const f2_t x = {ok[2 * it] ? v[2 * it] * o.scale : 0.0f, ok[2 * it + 1] ? v[2 * it + 1] * o.scale : 0.0f};
+    const int r = r_first + it * r_inc, k = k_first + it * k_inc;
+    const f2_t x = {v[2 * it] * scale, v[2 * it + 1] * scale};
     uint32_t hi, lo;
     split_bf16x2(x, hi, lo);
     *reinterpret_cast<uint32_t*>(&H[r][k]) = hi;
@@ -349,6 +379,9 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
   using Acc = typename P::Acc;
   constexpr int BM = 32 * WM, BN = 32 * WN, EA = BM * BK / NT, EB = BN * BK / NT;
   Smem<P, BM, BN>& sm = *reinterpret_cast<Smem<P, BM, BN>*>(smem);
+  // the wave index is uniform across its lanes: keep it (and the sub-tile
+  // predicates derived from it) scalar, so that inactive sub-tiles branch
+  // around their MFMAs instead of selecting whole accumulators
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
   const int lr = lane & 15, lk = lane >> 4;
@@ -389,18 +422,20 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
 #pragma unroll
         for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < WN; ++ni)
+          for (int ni = 0; ni < WN; ++ni) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
               if (r < Tk.M && c < Tk.N)
                 acc[mi][ni][v] += alpha * gld(tb ? B + (int64_t)c * Cb.ldb + r : B + (int64_t)r * Cb.ldb + c);
             }
+          }
       }
     }
 
-    // MFMA contributions, software pipelined: the next tile is fetched into
-    // registers while the current one is multiplied out of LDS.
+    // MFMA contributions.  The flattened (contribution, member, k tile)
+    // sequence streams through P::depth register sets: while step i is
+    // multiplied out of LDS, the loads of steps i+1 .. i+depth are in flight.
     auto first_from = [&](int ci) {
       while (ci < Tk.contrib_end && (contribs[ci].flags & GF_IDENT_A)) ++ci;
       return ci;
@@ -421,50 +456,57 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
         opnd_setup<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
       }
     };
-    Step cur{first_from(Tk.contrib_begin), 0, 0, 0};
-    if (cur.ci < Tk.contrib_end) {
+    // what staging a register set needs from the step it holds
+    struct SetMeta {
+      int kend;       // valid k in the tile
+      bool akc, bkc;  // operand tile is k-contiguous in memory
+      T scale;        // alpha of the contribution (applied to A)
+    };
+    Step lc{first_from(Tk.contrib_begin), 0, 0, 0};  // next step to load
+    if (lc.ci < Tk.contrib_end) {
       Opnd<T> oa, ob;
-      cur.K = contribs[cur.ci].K;
-      setup(cur, oa, ob);
-      T ra[EA], rb[EB];
-      bool ka[EA], kb[EB];
-      auto load = [&](int k0) {
+      lc.K = contribs[lc.ci].K;
+      setup(lc, oa, ob);
+      bool lmore = true;
+      T ra0[EA], rb0[EB], ra1[EA], rb1[EB];
+      SetMeta m0, m1;
+      // issue the loads of step lc into a register set, then advance lc
+      auto load_step = [&](T (&ra)[EA], T (&rb)[EB], SetMeta& m) {
+        m.kend = (lc.K - lc.k0 < BK) ? lc.K - lc.k0 : BK;
+        m.akc = oa.r_inc != 0 || oa.k_inc == 0;
+        m.bkc = ob.r_inc != 0 || ob.k_inc == 0;
+        m.scale = oa.scale;
         if constexpr (P::split) {
-          opnd_load_split(oa, k0, ra, ka);
-          opnd_load_split(ob, k0, rb, kb);
+          opnd_load_split(oa, lc.k0, ra);
+          opnd_load_split(ob, lc.k0, rb);
         } else {
-          opnd_load(oa, k0, ra, ka);
-          opnd_load(ob, k0, rb, kb);
+          opnd_load(oa, lc.k0, ra);
+          opnd_load(ob, lc.k0, rb);
+        }
+        lc.k0 += BK;
+        if (lc.k0 >= lc.K) {
+          lc.k0 = 0;
+          if (++lc.t >= contribs[lc.ci].nred) {
+            lc.t = 0;
+            lc.ci = first_from(lc.ci + 1);
+            lmore = lc.ci < Tk.contrib_end;
+          }
+          if (lmore) {
+            lc.K = contribs[lc.ci].K;
+            setup(lc, oa, ob);
+          }
         }
       };
-      load(0);
-      for (;;) {
+      auto stage = [&](const T (&ra)[EA], const T (&rb)[EB], const SetMeta& m) {
         if constexpr (P::split) {
-          opnd_store_split(oa, ra, ka, sm.Ah, sm.Al);
-          opnd_store_split(ob, rb, kb, sm.Bh, sm.Bl);
+          opnd_store_split<BM>(m.akc, m.scale, ra, sm.Ah, sm.Al);
+          opnd_store_split<BN>(m.bkc, T(1), rb, sm.Bh, sm.Bl);
         } else {
-          opnd_store(oa, ra, ka, sm.A);
-          opnd_store(ob, rb, kb, sm.B);
+          opnd_store<BM>(m.akc, m.scale, ra, sm.A);
+          opnd_store<BN>(m.bkc, T(1), rb, sm.B);
         }
-        __syncthreads();
-        const int kend = (cur.K - cur.k0 < BK) ? cur.K - cur.k0 : BK;
-        // advance and prefetch
-        Step nxt = cur;
-        nxt.k0 += BK;
-        bool more = true;
-        if (nxt.k0 >= nxt.K) {
-          nxt.k0 = 0;
-          if (++nxt.t >= contribs[nxt.ci].nred) {
-            nxt.t = 0;
-            nxt.ci = first_from(nxt.ci + 1);
-            more = nxt.ci < Tk.contrib_end;
-          }
-          if (more) {
-            nxt.K = contribs[nxt.ci].K;
-            setup(nxt, oa, ob);
-          }
-        }
-        if (more) load(nxt.k0);
+      };
+      auto multiply = [&](int kend) {
         if constexpr (P::split) {
           // one 16x16x32 step covers the whole k tile (entries past K are 0)
           if (any) {
@@ -526,9 +568,40 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
                 if (act[i][j]) acc[i][j] = mfma4(fa[i], fb[j], acc[i][j]);
           }
         }
-        __syncthreads();
-        if (!more) break;
-        cur = nxt;
+      };
+      load_step(ra0, rb0, m0);
+      if constexpr (P::depth == 1) {
+        for (;;) {
+          stage(ra0, rb0, m0);
+          __syncthreads();
+          const int kend = m0.kend;
+          const bool h0 = lmore;
+          if (h0) load_step(ra0, rb0, m0);
+          multiply(kend);
+          __syncthreads();
+          if (!h0) break;
+        }
+      } else {
+        bool h1 = lmore;
+        if (h1) load_step(ra1, rb1, m1);
+        for (;;) {
+          stage(ra0, rb0, m0);
+          __syncthreads();
+          int kend = m0.kend;
+          const bool h0 = lmore;
+          if (h0) load_step(ra0, rb0, m0);
+          multiply(kend);
+          __syncthreads();
+          if (!h1) break;
+          stage(ra1, rb1, m1);
+          __syncthreads();
+          kend = m1.kend;
+          h1 = lmore;
+          if (h1) load_step(ra1, rb1, m1);
+          multiply(kend);
+          __syncthreads();
+          if (!h0) break;
+        }
       }
     }
     // result element v of lane l in sub-tile (mi, ni): row RL*(l/16) + RV*v, column l%16
@@ -536,15 +609,16 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
 #pragma unroll
       for (int mi = 0; mi < WM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < WN; ++ni)
+        for (int ni = 0; ni < WN; ++ni) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
-            if (r < Tk.M && c < Tk.N) {
-              auto* dst = Cp + (int64_t)r * Tk.ldc + c;
-              auto val = (decltype(*dst + 0))acc[mi][ni][v];
-              if (Tk.accumulate & GT_ACCUM) val += gld(dst);
-              gst(dst, val);
+            for (int v = 0; v < 4; ++v) {
+              int r = m0 + wm + mi * 16 + lk * P::RL + v * P::RV, c = n0 + wn + ni * 16 + lr;
+              if (r < Tk.M && c < Tk.N) {
+                auto* dst = Cp + (int64_t)r * Tk.ldc + c;
+                auto val = (decltype(*dst + 0))acc[mi][ni][v];
+                if (Tk.accumulate & GT_ACCUM) val += gld(dst);
+                gst(dst, val);
+              }
             }
           }
     };
@@ -566,10 +640,10 @@ __global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ t
                                                   const typename P::T* p0, double* p1) {
   using SmemT = std::conditional_t<MIXED, Smem<P, 64, 64>, Smem<P, 32 * WM, 32 * WN>>;
   __shared__ SmemT smem;
+  __shared__ int64_t s_unit;
   const int xcd = blockIdx.x % NXCD;
-  const int64_t njobs = map.njobs[xcd];
   const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
-  for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) {
+  auto run = [&](int64_t job) {
     const GTask Tk = tasks[find_task(tasks, bucket, map.shift, job)];
     const int64_t local = job - Tk.job_begin + Tk.job_off;
     if constexpr (!MIXED) {
@@ -590,7 +664,27 @@ __global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ t
           break;
       }
     }
+  };
+  if (map.dynamic) {
+    const int64_t* __restrict__ U = map.units + map.unit_begin[xcd];
+    const int64_t nu = map.nunits[xcd];
+    for (;;) {
+      if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(map.counters + 64 * xcd, 1u);
+      __syncthreads();
+      const int64_t u = s_unit;
+      __syncthreads();
+      if (u >= nu) break;
+      const int64_t je = U[u + 1];
+      for (int64_t job = U[u]; job < je; ++job) run(job);
+    }
+  } else {
+    const int64_t njobs = map.njobs[xcd];
+    for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) run(job);
   }
+}
+
+__global__ void zero_counters_kernel(unsigned* c) {
+  if (threadIdx.x < NXCD) c[64 * threadIdx.x] = 0u;
 }
 
 template <class P>
@@ -613,10 +707,55 @@ static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, c
     case TILE_EDGE:
       hipLaunchKernelGGL((gemm_kernel<P, 2, 2, true>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
       break;
-
     default:
       throw Error(DMRG_EINVAL, "unknown GEMM tile shape");
   }
+}
+
+// Workgroups of one GEMM kernel variant resident per compute unit.
+template <class P>
+static int blocks_per_cu_of(int tile) {
+  static int cache[NTILE] = {0};
+  if (cache[tile] == 0) {
+    const void* f = nullptr;
+    switch (tile) {
+      case TILE_32x32:
+        f = reinterpret_cast<const void*>(&gemm_kernel<P, 1, 1, false>);
+        break;
+      case TILE_64x32:
+        f = reinterpret_cast<const void*>(&gemm_kernel<P, 2, 1, false>);
+        break;
+      case TILE_32x64:
+        f = reinterpret_cast<const void*>(&gemm_kernel<P, 1, 2, false>);
+        break;
+      case TILE_EDGE:
+        f = reinterpret_cast<const void*>(&gemm_kernel<P, 2, 2, true>);
+        break;
+      default:
+        f = reinterpret_cast<const void*>(&gemm_kernel<P, 2, 2, false>);
+        break;
+    }
+    int nb = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, NT, 0));
+    cache[tile] = nb > 0 ? nb : 1;
+  }
+  return cache[tile];
+}
+static int blocks_per_cu(int elem, int tile) {
+  DMRG_CHECK(tile >= 0 && tile < NTILE, DMRG_EINVAL, "unknown GEMM tile shape");
+  if (elem == P_F64) return blocks_per_cu_of<PolF64>(tile);
+  if (elem == P_F32) return blocks_per_cu_of<PolF32>(tile);
+  return blocks_per_cu_of<PolBF3>(tile);
+}
+static int cu_count() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    if (n < NXCD) n = NXCD;
+  }
+  return n;
 }
 
 void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
@@ -625,15 +764,22 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
   if (ntasks == 0 || map.max_jobs == 0) return;
   int64_t per = map.max_jobs < (1 << 19) ? map.max_jobs : (1 << 19);
   if (grid_per_xcd > 0 && grid_per_xcd < per) per = grid_per_xcd;
+  XcdMap m = map;
+  m.dynamic = grid_per_xcd < 0;
+  if (m.dynamic) {
+    DMRG_CHECK(map.units && map.counters, DMRG_EINVAL, "dynamic GEMM launch without units");
+    per = (int64_t)(cu_count() / NXCD) * blocks_per_cu(elem, tile);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, S(stream), map.counters);
+  }
   const dim3 grid((unsigned)(per * NXCD));
   if (elem == P_F64) {
-    launch_variant<PolF64>(tile, grid, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+    launch_variant<PolF64>(tile, grid, S(stream), tasks_dev, m, contribs_dev, bucket_dev,
                            (double* const*)table_dev, (const double*)p0, (double*)p1);
   } else if (elem == P_F32) {
-    launch_variant<PolF32>(tile, grid, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+    launch_variant<PolF32>(tile, grid, S(stream), tasks_dev, m, contribs_dev, bucket_dev,
                            (float* const*)table_dev, (const float*)p0, (double*)p1);
   } else if (elem == P_BF16X3) {
-    launch_variant<PolBF3>(tile, grid, S(stream), tasks_dev, map, contribs_dev, bucket_dev,
+    launch_variant<PolBF3>(tile, grid, S(stream), tasks_dev, m, contribs_dev, bucket_dev,
                            (float* const*)table_dev, (const float*)p0, (double*)p1);
   } else {
     throw Error(DMRG_EINVAL, "unknown GEMM precision");

@@ -879,7 +879,7 @@ void sigma_run(Ops& O, const double* psi, double* sigma, int prec, void* stream)
 void autotune_launches(size_t nl, const std::function<void(const std::vector<int>&, const std::vector<int64_t>&,
                                                            std::vector<double>&)>& run_all,
                        std::vector<int>& tiles, std::vector<int64_t>& grids, double& ms_default, double& ms_best) {
-  std::vector<double> ms(nl), best(nl, 1e300);
+  std::vector<double> ms(nl), best(nl, 1e300), ms_default_i(nl, 0.0);
   tiles.assign(nl, TILE_64x64);
   grids.assign(nl, 0);
   std::vector<int> tv(nl);
@@ -887,25 +887,25 @@ void autotune_launches(size_t nl, const std::function<void(const std::vector<int
   ms_default = 0;
   for (int t = 0; t < NTILE; ++t) {
     std::fill(tv.begin(), tv.end(), t);
-    run_all(tv, gv, ms);  // warm-up (uploads this shape)
-    run_all(tv, gv, ms);
-    for (size_t i = 0; i < nl; ++i) {
-      if (t == TILE_64x64) ms_default += ms[i];
-      if (ms[i] < best[i]) {
-        best[i] = ms[i];
-        tiles[i] = t;
+    // one workgroup per job (the first run also uploads this shape's lists),
+    // then resident workgroups taking cost-balanced units (grid -1)
+    for (int64_t g : {int64_t(0), int64_t(0), int64_t(-1)}) {
+      std::fill(gv.begin(), gv.end(), g);
+      run_all(tv, gv, ms);
+      for (size_t i = 0; i < nl; ++i) {
+        if (t == TILE_64x64 && g == 0) ms_default_i[i] = ms[i];
+        if (ms[i] < best[i]) {
+          best[i] = ms[i];
+          tiles[i] = t;
+          grids[i] = g;
+        }
       }
     }
   }
-  // persistent grid (8 workgroups per CU, 32 CUs per XCD) on the chosen shapes
-  std::fill(gv.begin(), gv.end(), int64_t(256));
-  run_all(tiles, gv, ms);
+  ms_default = 0;
   ms_best = 0;
   for (size_t i = 0; i < nl; ++i) {
-    if (ms[i] < 0.97 * best[i]) {
-      best[i] = ms[i];
-      grids[i] = 256;
-    }
+    ms_default += ms_default_i[i];
     ms_best += best[i];
   }
 }
