@@ -172,12 +172,14 @@ def cpu_baseline(ctx):
 def davidson_leg(ops, psi, mlp_path):
     """Davidson time to 1e-6 Eh from the seeded start vector.
 
-    Solvers: split-BF16 sigma (FP64 polish) with the learned preconditioner, the same
-    with the diagonal preconditioner, and plain FP64 sigma with the diagonal one.
-    E_ref is the energy of the first solver converged to ||r|| <= 1e-5 with FP64
-    sigma; its time to E_ref + 1e-6 comes from its trace, the other two stop there.
-    The FP32 operator copies and the per-bond feature tables are built before the
-    timed runs (they belong to the operator build)."""
+    Solvers: plain FP64 sigma with the textbook diagonal preconditioner
+    (kappa = 0); FP64 with the shifted diagonal preconditioner (kappa = 1, the
+    library default); split-BF16 sigma (FP64 polish) with the shifted diagonal
+    one; the same with the learned preconditioner.  E_ref is the energy of the
+    split-BF16 shifted run converged to ||r|| <= 1e-5 with FP64 sigma; its time to
+    E_ref + 1e-6 comes from its trace, the other solvers stop there.  The FP32
+    operator copies and the per-bond feature tables are built before the timed
+    runs (they belong to the operator build)."""
     import torch
     w = np.load(mlp_path).astype(np.float32)
     y = torch.empty(len(psi), dtype=torch.float64, device="cuda")
@@ -188,29 +190,32 @@ def davidson_leg(ops, psi, mlp_path):
     torch.cuda.synchronize()
     del t
     out = {"start": "seeded Gaussian psi (the bench input)", "mlp_weights": os.path.relpath(mlp_path, ROOT)}
-    log("[bench] davidson bf16x3_mlp (reference run) ...")
+    log("[bench] davidson bf16x3_shift (reference run) ...")
     x = torch.from_numpy(psi).cuda()
-    eref, st = ops.davidson(x.data_ptr(), trace=4000, precision=2, precond=1, mlp_weights=w,
-                            tol_residual=1e-5, max_iter=2000)
+    eref, st = ops.davidson(x.data_ptr(), trace=4000, precision=2, precond_shift=1.0, tol_residual=1e-5,
+                            max_iter=2000)
     tr = st["trace"]
     hit = np.nonzero((tr[:, 1] <= eref + 1e-6) & (tr[:, 3] == 0))[0]
     out["E_ref"] = eref
-    out["bf16x3_mlp"] = {"seconds_to_1e-6": float(tr[hit[0], 0]), "iterations_to_1e-6": int(hit[0] + 1),
-                       "switch_iter": st["switch_iter"], "mlp_fallbacks": st["mlp_fallbacks"],
-                       "seconds_total": st["seconds"], "iterations_total": st["iterations"],
-                       "residual": st["residual"], "converged": st["converged"]}
-    log(f"[bench] davidson bf16x3_mlp: {out['bf16x3_mlp']}")
-    for name, kw in (("plain_fp64_diag", {}), ("bf16x3_diag", {"precision": 2})):
+    out["bf16x3_shift"] = {"seconds_to_1e-6": float(tr[hit[0], 0]), "iterations_to_1e-6": int(hit[0] + 1),
+                           "switch_iter": st["switch_iter"], "seconds_total": st["seconds"],
+                           "iterations_total": st["iterations"], "residual": st["residual"],
+                           "converged": st["converged"]}
+    log(f"[bench] davidson bf16x3_shift: {out['bf16x3_shift']}")
+    for name, kw in (("plain_fp64_diag", {"precond_shift": 0.0}), ("fp64_shift", {"precond_shift": 1.0}),
+                     ("bf16x3_mlp_shift", {"precision": 2, "precond_shift": 1.0, "precond": 1, "mlp_weights": w})):
         log(f"[bench] davidson {name} ...")
         x = torch.from_numpy(psi).cuda()
         e, st = ops.davidson(x.data_ptr(), e_ref=eref, e_tol=1e-6, stop_at_ref=1, max_iter=2000,
                              tol_residual=1e-5, **kw)
         out[name] = {"seconds_to_1e-6": st["seconds_to_ref"], "iterations_to_1e-6": st["iters_to_ref"],
-                     "fp64_sigma_calls": st["sigma_fp64"], "switch_iter": st["switch_iter"], "E-E_ref": e - eref}
+                     "fp64_sigma_calls": st["sigma_fp64"], "switch_iter": st["switch_iter"],
+                     "mlp_fallbacks": st["mlp_fallbacks"], "E-E_ref": e - eref}
         log(f"[bench] davidson {name}: {out[name]}")
     t0 = out["plain_fp64_diag"]["seconds_to_1e-6"]
-    t1 = out["bf16x3_mlp"]["seconds_to_1e-6"]
-    out["speedup_bf16x3_mlp_vs_plain"] = (t0 / t1) if (t0 and t0 > 0 and t1 and t1 > 0) else None
+    for name in ("fp64_shift", "bf16x3_shift", "bf16x3_mlp_shift"):
+        t1 = out[name]["seconds_to_1e-6"]
+        out[f"speedup_{name}_vs_plain"] = (t0 / t1) if (t0 and t0 > 0 and t1 and t1 > 0) else None
     return out
 
 
@@ -227,7 +232,7 @@ def main():
     ap.add_argument("--x-budget-gb", type=float, default=0.0,
                     help="R-step scratch per slot in GB (0: library default)")
     ap.add_argument("--davidson", action="store_true",
-                    help="also time Davidson to 1e-6 Eh (plain FP64+diagonal vs split-BF16+learned preconditioner)")
+                    help="also time Davidson to 1e-6 Eh (plain FP64 + diagonal vs shifted, split-BF16, learned)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_02854_amd", "data", "precond_mlp.npy"),
                     help="learned preconditioner weights for --davidson")
     ap.add_argument("--copy-probe", action="store_true",

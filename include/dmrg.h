@@ -122,6 +122,13 @@ typedef struct {
   double* trace;           /* optional host array [trace_cap][4]: per iteration (seconds since
                               entry, Ritz value, ||r||_2, precision of the sigma behind it) */
   int trace_cap;
+  double precond_shift;    /* kappa >= 0: the correction divides by theta - kappa ||r||_2 - H_ii
+                              instead of theta - H_ii (default 1; 0 is the plain diagonal
+                              preconditioner).  Some eigenvalue lies within ||r||_2 of theta, so
+                              theta - ||r||_2 bounds the sought lowest one from below for
+                              kappa = 1; the shift keeps the denominators of components with
+                              H_ii near theta away from zero.  The learned preconditioner takes
+                              the shifted value as its theta (features and base correction). */
 } dmrg_davidson_opts;
 
 typedef struct {
@@ -259,7 +266,7 @@ int dmrg_mlp_nweights(void);
 int dmrg_mlp_init(float* weights, uint64_t seed);
 
 /* Training pairs from one bond.  Runs FP64 Davidson with the diagonal
- * preconditioner from psi0 (device, n_psi; not modified) for at most max_iter
+ * preconditioner (default shift) from psi0 (device, n_psi; not modified) for at most max_iter
  * sigma calls and, at every iteration, draws per_iter element indices
  * (seeded) and records for each: the features f_i, the diagonal correction
  * d_i, and the target s*e_i, where e is the part of the reference eigenvector

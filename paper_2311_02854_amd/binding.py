@@ -56,7 +56,7 @@ class DavidsonOpts(C.Structure):
                 ("precision", C.c_int), ("switch_residual", C.c_double), ("precond", C.c_int),
                 ("mlp_weights", C.POINTER(C.c_float)), ("e_ref", C.c_double), ("e_tol", C.c_double),
                 ("stop_at_ref", C.c_int), ("stagnation", C.c_int),
-                ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int)]
+                ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int), ("precond_shift", C.c_double)]
 
 
 class DavidsonStats(C.Structure):

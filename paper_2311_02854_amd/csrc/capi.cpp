@@ -236,6 +236,7 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts* o) {
   o->trace = nullptr;
   o->trace_cap = 0;
   o->precond = 0;
+  o->precond_shift = 1.0;
   o->mlp_weights = nullptr;
   o->e_ref = std::numeric_limits<double>::quiet_NaN();
   o->e_tol = 1e-6;

@@ -42,6 +42,8 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   DMRG_CHECK(opt.precision >= 0 && opt.precision <= 2, DMRG_EINVAL, "unknown precision");
   DMRG_CHECK(opt.precond == 0 || (opt.precond == 1 && opt.mlp_weights), DMRG_EINVAL,
              "precond 1 needs mlp_weights");
+  DMRG_CHECK(opt.precond_shift >= 0 && std::isfinite(opt.precond_shift), DMRG_EINVAL,
+             "precond_shift must be finite and >= 0");
   DBuf V((size_t)mmax * n), W((size_t)mmax * n), dg(n), x(n), hx(n), r(n), t(n), xp(n), hxp(n), sm(4 * 32 * 32 + 64);
   double* dvals = sm.p;            // dots
   double* dG = sm.p + 64;          // projected matrix
@@ -163,7 +165,9 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       break;
     }
     // correction vector
-    dev_h2d(dth, &theta, sizeof(double));
+    // shifted Ritz value of the preconditioner (the learned one sees it too)
+    const double theta_pc = theta - opt.precond_shift * rn;
+    dev_h2d(dth, &theta_pc, sizeof(double));
     if (hook) hook(x.p, r.p, dg.p, dth, V.p, m, iters);
     used_mlp = opt.precond == 1 && mlp_fail < 3;
     if (used_mlp)

@@ -2,8 +2,9 @@
 
 Training pairs come from Davidson runs of the method itself on the seeded
 synthetic workloads K8 (N=8, D=64), K24 (N=24, D=1000, several bonds) and K36
-(N=36, D=3000, mid-chain): every iteration of an FP64 diagonal-preconditioned
-run contributes sampled (features, diagonal correction, ideal correction)
+(N=36, D=3000, mid-chain): every iteration of an FP64 Davidson run with the
+library's default (shifted) diagonal preconditioner contributes sampled
+(features, diagonal correction, ideal correction)
 triples (dmrg_mlp_collect); the reference eigenvector behind the ideal
 correction is the converged Davidson vector of the same problem (FP32 sigma,
 then FP64 to ||r|| <= 1e-6).  The

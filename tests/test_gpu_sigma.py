@@ -102,14 +102,16 @@ def test_diag_vs_oracle(ctx):
     assert err <= 1e-10, err
 
 
-def test_davidson_reaches_fci(ctx):
+@pytest.mark.parametrize("kappa", [0.0, 1.0])   # plain diagonal and shifted preconditioner
+def test_davidson_reaches_fci(ctx, kappa):
     import torch
     ints, mps, psi = problem(8, 4, 4, 64, 3, 1)
     ops = ctx.build_ops(ints, mps)
     H, _ = fock.hamiltonian(ints["h"], ints["eri"], 4, 4)
     efci = fock.fci_energy(H)
     x = torch.from_numpy(psi).cuda()
-    e, st = ops.davidson(x.data_ptr(), tol_residual=1e-7, max_iter=400)
+    e, st = ops.davidson(x.data_ptr(), tol_residual=1e-7, max_iter=400, precond_shift=kappa)
+    print(f"kappa={kappa}: {st['iterations']} iterations")
     assert st["converged"]
     assert abs(e - efci) < 1e-9
     v = x.cpu().numpy()
@@ -117,6 +119,17 @@ def test_davidson_reaches_fci(ctx):
     # returned vector is an eigenvector: residual from the oracle's sigma
     r = blocks.TwoDotBlocks(ints, mps).sigma(v) - e * v
     assert np.linalg.norm(r) < 1e-6
+
+
+def test_davidson_rejects_negative_shift(ctx):
+    import torch
+    from paper_2311_02854_amd.binding import DmrgError
+    ints, mps, psi = problem(8, 4, 4, 64, 3, 1)
+    ops = ctx.build_ops(ints, mps)
+    x = torch.from_numpy(psi).cuda()
+    with pytest.raises(DmrgError):
+        ops.davidson(x.data_ptr(), precond_shift=-1.0)
+    assert np.array_equal(x.cpu().numpy(), psi)
 
 
 def test_config2_hermitian_deterministic(ctx):
