@@ -143,16 +143,31 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     prev_theta = theta;
     const double switch_at = std::max(opt.switch_residual, floor_rel(prec) * std::fabs(theta));
     if (prec != P_F64 && (rn <= switch_at || stagnant >= stag_max)) {
-      // switch to FP64 sigma: restart from the Ritz vector with an exact image
+      // switch to FP64 sigma: restart from the Ritz vector and the previous
+      // one (as at a subspace restart), both with exact images
       prec = P_F64;
       switch_iter = iters;
+      if (have_prev) {
+        std::vector<double> yp(m, 0.0);
+        for (int i = 0; i < m - 1; ++i) yp[i] = yprev[i];
+        dev_h2d(dy, yp.data(), sizeof(double) * m);
+        k_lincomb(V.p, n, m, dy, n, xp.p, stream);
+      }
       k_copy(x.p, Vp(0), n, stream);
       double nx = std::sqrt(ddot(Vp(0), Vp(0), n, dvals, stream));
       k_scale(Vp(0), 1.0 / nx, n, stream);
-      sig(Vp(0), Wp(0), prec);
-      ++iters;
-      ++iters64;
-      m = 1;
+      int mnew = 1;
+      if (have_prev) {
+        k_copy(xp.p, Vp(1), n, stream);
+        const double np = orth_normalize(Vp(1), 1);
+        if (np > 1e-3 && std::isfinite(np)) mnew = 2;
+      }
+      for (int j = 0; j < mnew; ++j) {
+        sig(Vp(j), Wp(j), prec);
+        ++iters;
+        ++iters64;
+      }
+      m = mnew;
       have_prev = false;
       used_mlp = false;
       rn = 1e300;

@@ -246,6 +246,11 @@ class GemmList {
         ncontribs_dev_ = contribs.size();
       }
     }
+    // the kernel addresses an operand tile with 32-bit byte offsets from the
+    // tile's first row: at most 128 rows (or k) of the leading dimension
+    for (const GContrib& c : contribs)
+      DMRG_CHECK(c.lda < (1 << 20) && c.ldb < (1 << 20) && c.K < (1 << 20), DMRG_ESHAPE,
+                 "GEMM leading dimension or K too large for 32-bit tile offsets");
     std::memset(&D.map, 0, sizeof(D.map));
     std::vector<GTask> dev;
     std::vector<double> cj(src.size());

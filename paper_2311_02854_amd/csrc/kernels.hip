@@ -213,64 +213,75 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
 }
 
 // Per-thread view of one ROWS x BK operand tile: element (r, k) of op(X) sits
-// at X + r*sr + k*sk.  When k is contiguous (sk == 1) threads walk k fastest
-// (32 per row, 8 rows per pass), otherwise r fastest (ROWS per row, 256/ROWS
-// k per pass); either way every thread owns E = ROWS*BK/256 elements.
+// at X + r*sr + k*sk.  When k is contiguous (kc: sk == 1) threads walk k
+// fastest (32 per row, 8 rows per pass), otherwise r fastest (ROWS per row,
+// 256/ROWS k per pass); either way every thread owns E = ROWS*BK/256 elements.
+//
+// Loads go through a buffer descriptor based at the tile's first row whose
+// range ends at the operand's last valid element (row rows-1, column K-1):
+// elements outside it read as zero and nothing is ever read past that
+// element.  Along the outer dimension of the storage (rows when kc, k
+// otherwise) the range check therefore zeroes every element past the operand.
+// Inside it, a kc tile's k tail (k >= K) holds neighbouring values of the
+// same matrix: the LDS store zeroes it (one compare per thread: all of a
+// thread's elements share one k); a row-contiguous tile's rows past the
+// operand hold neighbouring values too, which only reach output rows or
+// columns that are never stored.
 template <typename T>
 struct Opnd {
-  const T* origin;   // element (0, 0) of op(X): always a valid address
-  const T* base;     // element (r_first, k_first) at k0 = 0
-  int64_t step_it;   // distance between a thread's consecutive elements
-  int64_t step_k;    // distance of one BK tile
-  int r_first, k_first;
+  __amdgpu_buffer_rsrc_t rsrc;
+  int32_t lane_off;  // byte offset of the thread's first element at k0 = 0
+  int32_t step_it;   // bytes between a thread's consecutive elements
+  int32_t step_k;    // bytes of one BK tile
+  int32_t s2;        // split staging: bytes from a pair's first to its second element
   int r_inc, k_inc;  // increments per element (one of them is 0)
-  int rows, K;       // valid extent (rows counted from the tile origin)
   T scale;
-  int64_t s2;        // split staging: distance from a pair's first to its second element
 };
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const T* origin, int64_t sr, int64_t sk, int rv, int K) {
+  const int64_t last = sk == 1 ? (int64_t)(rv - 1) * sr + (K - 1) : (int64_t)(K - 1) * sk + (rv - 1);
+  const int64_t bytes = (rv > 0 && K > 0) ? (last + 1) * (int64_t)sizeof(T) : 0;  // empty: every load reads 0
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(origin), (short)0, (int)bytes, 0x00020000);
+}
 
 template <int ROWS, typename T>
 __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, int64_t sk, int r0, int rows,
                                            int K, T scale) {
   const int tid = threadIdx.x;
+  int r_first, k_first;
   if (sk == 1) {
-    o.r_first = tid >> 5;
-    o.k_first = tid & 31;
+    r_first = tid >> 5;
+    k_first = tid & 31;
     o.r_inc = 8;
     o.k_inc = 0;
-    o.step_it = 8 * sr;
+    o.step_it = (int32_t)(8 * sr * (int64_t)sizeof(T));
   } else {
-    o.r_first = tid % ROWS;
-    o.k_first = tid / ROWS;
+    r_first = tid % ROWS;
+    k_first = tid / ROWS;
     o.r_inc = 0;
     o.k_inc = NT / ROWS;
-    o.step_it = (NT / ROWS) * sk;
+    o.step_it = (int32_t)((NT / ROWS) * sk * (int64_t)sizeof(T));
   }
-  o.origin = X;
-  o.base = X + (int64_t)(r0 + o.r_first) * sr + (int64_t)o.k_first * sk;
-  o.step_k = (int64_t)BK * sk;
-  o.rows = rows - r0;
-  o.K = K;
+  const T* origin = X + (int64_t)r0 * sr;
+  o.rsrc = tile_rsrc(origin, sr, sk, rows - r0, K);
+  o.lane_off = (int32_t)(((int64_t)r_first * sr + (int64_t)k_first * sk) * (int64_t)sizeof(T));
+  o.step_k = (int32_t)((int64_t)BK * sk * (int64_t)sizeof(T));
   o.scale = scale;
 }
 
-// Out-of-range elements load from a page of zeros, so a tile needs no mask
-// between its loads and its LDS store: the loads issue back to back without
-// branches, and a register set can wait in flight while another is staged.
-__device__ const double g_zero_page[2] = {0.0, 0.0};
-template <typename T>
-__device__ __forceinline__ const T* zero_page() {
-  return reinterpret_cast<const T*>(g_zero_page);
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, int32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
 template <int E, typename T>
 __device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E]) {
-  const T* p = o.base + (int64_t)(k0 / BK) * o.step_k;
+  const int32_t off = o.lane_off + (k0 / BK) * o.step_k;
 #pragma unroll
-  for (int it = 0; it < E; ++it) {
-    const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
-    v[it] = gld(((r < o.rows) & (k < o.K)) ? p + it * o.step_it : zero_page<T>());
-  }
+  for (int it = 0; it < E; ++it) v[it] = buf_load(o.rsrc, off + it * o.step_it, T(0));
 }
 
 // Element it of a thread's share of a ROWS x BK tile sits at (row, k) =
@@ -285,12 +296,14 @@ __device__ __forceinline__ void tile_pattern(bool kc, int& r_first, int& k_first
   k_inc = kc ? 0 : NT / ROWS;
 }
 
+// kvalid: valid k of this tile (the k tail of a kc tile is zeroed here)
 template <int ROWS, int E, typename T, int LD>
-__device__ __forceinline__ void opnd_store(bool kc, T scale, const T (&v)[E], T (*L)[LD]) {
+__device__ __forceinline__ void opnd_store(bool kc, int kvalid, T scale, const T (&v)[E], T (*L)[LD]) {
   int r_first, k_first, r_inc, k_inc;
   tile_pattern<ROWS>(kc, r_first, k_first, r_inc, k_inc);
+  const bool keep = !kc || k_first < kvalid;
 #pragma unroll
-  for (int it = 0; it < E; ++it) L[k_first + it * k_inc][r_first + it * r_inc] = v[it] * scale;
+  for (int it = 0; it < E; ++it) L[k_first + it * k_inc][r_first + it * r_inc] = keep ? v[it] * scale : T(0);
 }
 
 // Split-BF16 staging: every thread owns E/2 pairs of k-consecutive elements
@@ -301,38 +314,35 @@ template <int ROWS>
 __device__ __forceinline__ void opnd_setup_split(Opnd<float>& o, const float* X, int64_t sr, int64_t sk, int r0,
                                                  int rows, int K, float scale) {
   const int tid = threadIdx.x;
+  int r_first, k_first;
   if (sk == 1) {
-    o.r_first = tid >> 4;
-    o.k_first = 2 * (tid & 15);
+    r_first = tid >> 4;
+    k_first = 2 * (tid & 15);
     o.r_inc = NT / 16;
     o.k_inc = 0;
-    o.step_it = (NT / 16) * sr;
+    o.step_it = (int32_t)((NT / 16) * sr * 4);
   } else {
-    o.r_first = tid % ROWS;
-    o.k_first = 2 * (tid / ROWS);
+    r_first = tid % ROWS;
+    k_first = 2 * (tid / ROWS);
     o.r_inc = 0;
     o.k_inc = 2 * NT / ROWS;
-    o.step_it = (2 * NT / ROWS) * sk;
+    o.step_it = (int32_t)((2 * NT / ROWS) * sk * 4);
   }
-  o.s2 = sk;
-  o.origin = X;
-  o.base = X + (int64_t)(r0 + o.r_first) * sr + (int64_t)o.k_first * sk;
-  o.step_k = (int64_t)BK * sk;
-  o.rows = rows - r0;
-  o.K = K;
+  o.s2 = (int32_t)(sk * 4);
+  const float* origin = X + (int64_t)r0 * sr;
+  o.rsrc = tile_rsrc(origin, sr, sk, rows - r0, K);
+  o.lane_off = (int32_t)(((int64_t)r_first * sr + (int64_t)k_first * sk) * 4);
+  o.step_k = (int32_t)((int64_t)BK * sk * 4);
   o.scale = scale;
 }
 
 template <int E>
 __device__ __forceinline__ void opnd_load_split(const Opnd<float>& o, int k0, float (&v)[E]) {
-  const float* p = o.base + (int64_t)(k0 / BK) * o.step_k;
+  const int32_t off = o.lane_off + (k0 / BK) * o.step_k;
 #pragma unroll
   for (int it = 0; it < E / 2; ++it) {
-    const int r = o.r_first + it * o.r_inc, k = k0 + o.k_first + it * o.k_inc;
-    const bool rv = r < o.rows;
-    const float* q = p + it * o.step_it;
-    v[2 * it] = gld((rv & (k < o.K)) ? q : zero_page<float>());
-    v[2 * it + 1] = gld((rv & (k + 1 < o.K)) ? q + o.s2 : zero_page<float>());
+    v[2 * it] = buf_load(o.rsrc, off + it * o.step_it, 0.0f);
+    v[2 * it + 1] = buf_load(o.rsrc, off + it * o.step_it + o.s2, 0.0f);
   }
 }
 
@@ -346,14 +356,15 @@ __device__ __forceinline__ void tile_pattern_split(bool kc, int& r_first, int& k
 }
 
 template <int ROWS, int E, int LD>
-__device__ __forceinline__ void opnd_store_split(bool kc, float scale, const float (&v)[E], uint16_t (*H)[LD],
-                                                 uint16_t (*Lo)[LD]) {
+__device__ __forceinline__ void opnd_store_split(bool kc, int kvalid, float scale, const float (&v)[E],
+                                                 uint16_t (*H)[LD], uint16_t (*Lo)[LD]) {
   int r_first, k_first, r_inc, k_inc;
   tile_pattern_split<ROWS>(kc, r_first, k_first, r_inc, k_inc);
+  const bool keep0 = !kc || k_first < kvalid, keep1 = !kc || k_first + 1 < kvalid;
 #pragma unroll
   for (int it = 0; it < E / 2; ++it) {
     const int r = r_first + it * r_inc, k = k_first + it * k_inc;
-    const f2_t x = {v[2 * it] * scale, v[2 * it + 1] * scale};
+    const f2_t x = {keep0 ? v[2 * it] * scale : 0.0f, keep1 ? v[2 * it + 1] * scale : 0.0f};
     uint32_t hi, lo;
     split_bf16x2(x, hi, lo);
     *reinterpret_cast<uint32_t*>(&H[r][k]) = hi;
@@ -499,11 +510,11 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
       };
       auto stage = [&](const T (&ra)[EA], const T (&rb)[EB], const SetMeta& m) {
         if constexpr (P::split) {
-          opnd_store_split<BM>(m.akc, m.scale, ra, sm.Ah, sm.Al);
-          opnd_store_split<BN>(m.bkc, T(1), rb, sm.Bh, sm.Bl);
+          opnd_store_split<BM>(m.akc, m.kend, m.scale, ra, sm.Ah, sm.Al);
+          opnd_store_split<BN>(m.bkc, m.kend, T(1), rb, sm.Bh, sm.Bl);
         } else {
-          opnd_store<BM>(m.akc, m.scale, ra, sm.A);
-          opnd_store<BN>(m.bkc, T(1), rb, sm.B);
+          opnd_store<BM>(m.akc, m.kend, m.scale, ra, sm.A);
+          opnd_store<BN>(m.bkc, m.kend, T(1), rb, sm.B);
         }
       };
       auto multiply = [&](int kend) {
