@@ -246,11 +246,12 @@ class GemmList {
         ncontribs_dev_ = contribs.size();
       }
     }
-    // the kernel addresses an operand tile with 32-bit byte offsets from the
-    // tile's first row: at most 128 rows (or k) of the leading dimension
+    // the kernel addresses one k tile of an operand with 32-bit byte offsets
+    // from its first element: at most 64 rows (or 32 k) of the leading
+    // dimension, which must stay below 2^21 elements
     for (const GContrib& c : contribs)
-      DMRG_CHECK(c.lda < (1 << 20) && c.ldb < (1 << 20) && c.K < (1 << 20), DMRG_ESHAPE,
-                 "GEMM leading dimension or K too large for 32-bit tile offsets");
+      DMRG_CHECK(c.lda < (1 << 21) && c.ldb < (1 << 21), DMRG_ESHAPE,
+                 "GEMM leading dimension too large for 32-bit tile offsets (limit 2^21 elements)");
     std::memset(&D.map, 0, sizeof(D.map));
     std::vector<GTask> dev;
     std::vector<double> cj(src.size());

@@ -217,8 +217,8 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
 // fastest (32 per row, 8 rows per pass), otherwise r fastest (ROWS per row,
 // 256/ROWS k per pass); either way every thread owns E = ROWS*BK/256 elements.
 //
-// Loads go through a buffer descriptor based at the tile's first row whose
-// range ends at the operand's last valid element (row rows-1, column K-1):
+// Loads go through a buffer descriptor based at the k tile's first element
+// whose range ends at the operand's last valid element among the tile's rows:
 // elements outside it read as zero and nothing is ever read past that
 // element.  Along the outer dimension of the storage (rows when kc, k
 // otherwise) the range check therefore zeroes every element past the operand.
@@ -229,20 +229,37 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
 // columns that are never stored.
 template <typename T>
 struct Opnd {
-  __amdgpu_buffer_rsrc_t rsrc;
-  int32_t lane_off;  // byte offset of the thread's first element at k0 = 0
-  int32_t step_it;   // bytes between a thread's consecutive elements
-  int32_t step_k;    // bytes of one BK tile
-  int32_t s2;        // split staging: bytes from a pair's first to its second element
-  int r_inc, k_inc;  // increments per element (one of them is 0)
+  const char* origin;  // element (0, 0) of the tile (first row, k = 0)
+  int64_t range;       // bytes from origin to the end of the last element a load may read
+  int64_t step_k;      // bytes of one BK tile
+  int32_t lane_off;    // byte offset of the thread's first element within a k tile
+  int32_t step_it;     // bytes between a thread's consecutive elements
+  int32_t s2;          // split staging: bytes from a pair's first to its second element
+  int r_inc, k_inc;    // increments per element (one of them is 0)
   T scale;
 };
 
-template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const T* origin, int64_t sr, int64_t sk, int rv, int K) {
+// Byte range of a tile: up to the operand's last valid element among the
+// tile's rows (at most ROWS of them) -- row min(rows, ROWS) - 1, column K - 1.
+template <int ROWS, typename T>
+__device__ __forceinline__ int64_t tile_range(int64_t sr, int64_t sk, int rv, int K) {
+  rv = rv < ROWS ? rv : ROWS;
+  if (rv <= 0 || K <= 0) return 0;
   const int64_t last = sk == 1 ? (int64_t)(rv - 1) * sr + (K - 1) : (int64_t)(K - 1) * sk + (rv - 1);
-  const int64_t bytes = (rv > 0 && K > 0) ? (last + 1) * (int64_t)sizeof(T) : 0;  // empty: every load reads 0
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(origin), (short)0, (int)bytes, 0x00020000);
+  return (last + 1) * (int64_t)sizeof(T);
+}
+
+// Descriptor of k tile k0 / BK: based at its first element, so that the
+// 32-bit offsets stay inside one tile whatever K and the strides are.  A range
+// beyond 2^31 - 1 bytes is capped: the tile never reads that far (leading
+// dimensions are below 2^20), and the zeroed elements past the operand all lie
+// in the last k tile, whose remaining range is small.
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const Opnd<T>& o, int k0) {
+  const int64_t kb = (int64_t)(k0 / BK) * o.step_k;
+  int64_t rem = o.range - kb;
+  rem = rem < 0 ? 0 : (rem > 0x7fffffff ? 0x7fffffff : rem);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(o.origin + kb), (short)0, (int)rem, 0x00020000);
 }
 
 template <int ROWS, typename T>
@@ -263,10 +280,10 @@ __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, i
     o.k_inc = NT / ROWS;
     o.step_it = (int32_t)((NT / ROWS) * sk * (int64_t)sizeof(T));
   }
-  const T* origin = X + (int64_t)r0 * sr;
-  o.rsrc = tile_rsrc(origin, sr, sk, rows - r0, K);
+  o.origin = reinterpret_cast<const char*>(X + (int64_t)r0 * sr);
+  o.range = tile_range<ROWS, T>(sr, sk, rows - r0, K);
   o.lane_off = (int32_t)(((int64_t)r_first * sr + (int64_t)k_first * sk) * (int64_t)sizeof(T));
-  o.step_k = (int32_t)((int64_t)BK * sk * (int64_t)sizeof(T));
+  o.step_k = (int64_t)BK * sk * (int64_t)sizeof(T);
   o.scale = scale;
 }
 
@@ -279,9 +296,9 @@ __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int32_t off,
 
 template <int E, typename T>
 __device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E]) {
-  const int32_t off = o.lane_off + (k0 / BK) * o.step_k;
+  const __amdgpu_buffer_rsrc_t r = tile_rsrc(o, k0);
 #pragma unroll
-  for (int it = 0; it < E; ++it) v[it] = buf_load(o.rsrc, off + it * o.step_it, T(0));
+  for (int it = 0; it < E; ++it) v[it] = buf_load(r, o.lane_off + it * o.step_it, T(0));
 }
 
 // Element it of a thread's share of a ROWS x BK tile sits at (row, k) =
@@ -329,20 +346,20 @@ __device__ __forceinline__ void opnd_setup_split(Opnd<float>& o, const float* X,
     o.step_it = (int32_t)((2 * NT / ROWS) * sk * 4);
   }
   o.s2 = (int32_t)(sk * 4);
-  const float* origin = X + (int64_t)r0 * sr;
-  o.rsrc = tile_rsrc(origin, sr, sk, rows - r0, K);
+  o.origin = reinterpret_cast<const char*>(X + (int64_t)r0 * sr);
+  o.range = tile_range<ROWS, float>(sr, sk, rows - r0, K);
   o.lane_off = (int32_t)(((int64_t)r_first * sr + (int64_t)k_first * sk) * 4);
-  o.step_k = (int32_t)((int64_t)BK * sk * 4);
+  o.step_k = (int64_t)BK * sk * 4;
   o.scale = scale;
 }
 
 template <int E>
 __device__ __forceinline__ void opnd_load_split(const Opnd<float>& o, int k0, float (&v)[E]) {
-  const int32_t off = o.lane_off + (k0 / BK) * o.step_k;
+  const __amdgpu_buffer_rsrc_t r = tile_rsrc(o, k0);
 #pragma unroll
   for (int it = 0; it < E / 2; ++it) {
-    v[2 * it] = buf_load(o.rsrc, off + it * o.step_it, 0.0f);
-    v[2 * it + 1] = buf_load(o.rsrc, off + it * o.step_it + o.s2, 0.0f);
+    v[2 * it] = buf_load(r, o.lane_off + it * o.step_it, 0.0f);
+    v[2 * it + 1] = buf_load(r, o.lane_off + it * o.step_it + o.s2, 0.0f);
   }
 }
 
