@@ -33,6 +33,9 @@ DEFAULT_OUT = os.path.join(HERE, "data", "precond_mlp.npy")
 TRAIN = [(8, 4, 4, 64, 3, 1)] + [(24, 12, 12, 1000, b, 2) for b in (5, 8, 11, 14, 17)] + \
         [(36, 18, 18, 3000, 17, 3)]
 HOLDOUT = (24, 12, 12, 1000, 13, 2)
+# with --large: two bonds of the K73 (N=114, D=2000) workload, next to the
+# middle bond the Davidson benchmark solves (which stays held out)
+LARGE = [(73, 57, 57, 2000, 32, 5), (73, 57, 57, 2000, 39, 5)]
 
 
 def log(*a):
@@ -63,6 +66,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--quick", action="store_true", help="K8 and one K24 bond only")
+    ap.add_argument("--large", action="store_true", help="also two K73 bonds (D=2000)")
     ap.add_argument("--iters", type=int, default=80, help="Davidson iterations sampled per problem")
     ap.add_argument("--per-iter", type=int, default=2048)
     ap.add_argument("--epochs", type=int, default=20)
@@ -72,13 +76,15 @@ def main():
 
     ctx = gpu_context(0)
     train = TRAIN[:2] if args.quick else TRAIN
+    if args.large:
+        train = train + LARGE
     feats, dcs, tgs, meta = [], [], [], []
     for spec in train:
         t0 = time.time()
         log(f"[train] K={spec[0]} D={spec[3]} bond={spec[4]}: building operators")
         ops, psi = problem(ctx, *spec)
         log(f"[train]   reference eigenvector ({time.time() - t0:.1f}s)")
-        xref, eref, st = reference(ops, psi)
+        xref, eref, st = reference(ops, psi, tol=1e-5 if spec[0] > 40 else 1e-6)
         log(f"[train]   collecting pairs ({time.time() - t0:.1f}s)")
         x0 = torch.from_numpy(psi).cuda()
         f, d, y = ops.mlp_collect(x0.data_ptr(), xref.data_ptr(), args.iters, args.per_iter,
