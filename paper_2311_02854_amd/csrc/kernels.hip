@@ -672,7 +672,7 @@ __global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ t
   const int xcd = blockIdx.x % NXCD;
   const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
   auto run = [&](int64_t job) {
-    const GTask Tk = tasks[find_task(tasks, bucket, map.shift, job)];
+    const GTask& Tk = tasks[find_task(tasks, bucket, map.shift, job)];
     const int64_t local = job - Tk.job_begin + Tk.job_off;
     if constexpr (!MIXED) {
       gemm_job<P, WM, WN>(Tk, local, &smem, contribs, table, p0, p1);
