@@ -109,8 +109,8 @@ typedef struct {
   int m_max;               /* subspace size before restart, 4..32, default 24 */
   int precision;           /* dmrg_precision of sigma in early iterations */
   double switch_residual;  /* reduced precision used while ||r|| > max(switch_residual,
-                              f |theta|), f = 6e-6 (FP32) or 1.5e-5 (BF16x3): a few times the
-                              measured relative sigma error of the format */
+                              f |theta|), f = 6e-6 (FP32) or 8e-6 (BF16x3): about 2-3 times the
+                              largest relative sigma error measured for the format */
   int precond;             /* 0 diagonal, 1 learned MLP (falls back to diagonal) */
   const float* mlp_weights;/* host weights for precond == 1 (dmrg_mlp_nweights floats) */
   double e_ref;            /* if finite: record time/iterations to reach e_ref + e_tol */

@@ -58,7 +58,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   const int stag_max = opt.stagnation > 0 ? opt.stagnation : 4;
   // residual floor of reduced-precision sigma relative to |theta|: a few times
   // the relative sigma error measured for each format
-  auto floor_rel = [](int p) { return p == P_F32 ? 6e-6 : (p == P_BF16X3 ? 1.5e-5 : 0.0); };
+  auto floor_rel = [](int p) { return p == P_F32 ? 6e-6 : (p == P_BF16X3 ? 8e-6 : 0.0); };
 
   auto sig = [&](const double* in, double* out, int p) { sigma_run(O, in, out, p, stream); };
   auto Vp = [&](int j) { return V.p + (int64_t)j * n; };
