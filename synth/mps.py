@@ -256,3 +256,85 @@ def make_psi(mps, seed):
     rng = np.random.default_rng(seed)
     v = rng.normal(size=n)
     return v / np.linalg.norm(v)
+
+
+def make_det_mps(K, Na, Nb, D, k, seed, mix=True):
+    """MPS whose renormalized states are (nearly) single determinants.
+
+    Same sectors as make_mps, but every site tensor is a selection isometry:
+    each new left (right) state is one distinct (old state, site state) pair
+    of its sector, so every state of sites 0..j is a single occupation string.
+    The pairs are taken old-state-first (lowest old index, ties in random
+    order) and then shuffled into state order: states built from the first
+    states of every sector stay close to each other, so the renormalized
+    operators between them have many nonzero elements.  With mix, the two
+    sites next to the dots (k-1 on the left, k+2 on the right) rotate pairs
+    of selected columns (rows) by random angles instead, so each state at
+    the dots is a combination of at most two strings.  The tensors stay
+    left- (right-) canonical.  Input data only: used to pin the block path
+    against an independent determinant-space evaluation at full size.
+    """
+    assert 0 <= k <= K - 2
+    dims = bond_sectors(K, Na, Nb, D, k)
+    sectors = [np.array([(q[0], q[1], d) for q, d in sorted(dd.items())], np.int64).reshape(-1, 3)
+               for dd in dims]
+    mps = SiteMPS(K, Na, Nb, D, k, sectors)
+    rng = np.random.default_rng(seed)
+
+    def select(cands, d):
+        # cands: list of (old_index, key); pick d, lowest old index first
+        tie = rng.random(len(cands))
+        order = sorted(range(len(cands)), key=lambda i: (cands[i][0], tie[i]))[:d]
+        return [cands[i][1] for i in rng.permutation(order)]
+
+    def rotated(nrow, picks, do_mix):
+        # isometry with columns e_{picks[c]} (pairs rotated when do_mix)
+        Q = np.zeros((nrow, len(picks)))
+        c = 0
+        while c < len(picks):
+            if do_mix and c + 1 < len(picks):
+                th = rng.uniform(0.2, 1.3)
+                x, y = picks[c], picks[c + 1]
+                Q[x, c], Q[y, c] = np.cos(th), np.sin(th)
+                Q[x, c + 1], Q[y, c + 1] = -np.sin(th), np.cos(th)
+                c += 2
+            else:
+                Q[picks[c], c] = 1.0
+                c += 1
+        return Q
+
+    for j in range(K):
+        if j in (k, k + 1):
+            continue
+        blocks = _site_blocks(mps, j)
+        store = {}
+        if j < k:
+            for ir in range(len(sectors[j + 1])):
+                rows = [(il, n) for (il, n, r) in blocks if r == ir]
+                cands, pos = [], 0
+                for il, n in rows:
+                    for l in range(mps.dim(j, il)):
+                        cands.append((l, pos + l))
+                    pos += mps.dim(j, il)
+                Q = rotated(pos, select(cands, mps.dim(j + 1, ir)), mix and j == k - 1)
+                pos = 0
+                for il, n in rows:
+                    dl = mps.dim(j, il)
+                    store[(il, n, ir)] = np.ascontiguousarray(Q[pos:pos + dl])
+                    pos += dl
+        else:
+            for il in range(len(sectors[j])):
+                cols = [(n, ir) for (l, n, ir) in blocks if l == il]
+                cands, pos = [], 0
+                for n, ir in cols:
+                    for r in range(mps.dim(j + 1, ir)):
+                        cands.append((r, pos + r))
+                    pos += mps.dim(j + 1, ir)
+                At = rotated(pos, select(cands, mps.dim(j, il)), mix and j == k + 2).T
+                pos = 0
+                for n, ir in cols:
+                    dr = mps.dim(j + 1, ir)
+                    store[(il, n, ir)] = np.ascontiguousarray(At[:, pos:pos + dr])
+                    pos += dr
+        mps.sites[j] = [(il, n, ir, store[(il, n, ir)]) for (il, n, ir) in blocks]
+    return mps

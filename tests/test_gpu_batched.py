@@ -11,12 +11,15 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import blocks
+from oracle import blocks, detci
+from parity import assert_close
+from synth.mps import make_det_mps
 
 pytestmark = pytest.mark.gpu
 
 SPECS = [(8, 4, 4, 64, 3, 1), (10, 5, 5, 64, 4, 3), (12, 6, 6, 200, 4, 6), (8, 3, 5, 24, 5, 2),
          (16, 8, 8, 256, 7, 16)]
+DET = 4   # this problem uses a determinant MPS: its oracle is O2 over every row
 X_BUDGET = 8 << 20   # small R-step scratch: several chunks, so problems differ in launch count
 
 
@@ -30,9 +33,9 @@ def ctx():
 def probs(ctx):
     import torch
     out = []
-    for (K, Na, Nb, D, k, seed) in SPECS:
+    for i, (K, Na, Nb, D, k, seed) in enumerate(SPECS):
         ints = synth.make_integrals(K, 1000 + seed)
-        mps = synth.make_mps(K, Na, Nb, D, k, 3000 + seed)
+        mps = (make_det_mps if i == DET else synth.make_mps)(K, Na, Nb, D, k, 3000 + seed)
         psi = synth.make_psi(mps, 2000 + seed)
         ops = ctx.build_ops(ints, mps, x_budget=X_BUDGET)
         out.append((ints, mps, ops, torch.from_numpy(psi).cuda()))
@@ -57,11 +60,29 @@ def batched(ctx, probs, xs, prec, flags=0, ys=None):
     return ys, [y.cpu().numpy() for y in ys]
 
 
-def test_small_budget_still_matches_oracle(probs):
-    ints, mps, ops, x = probs[2]
-    s = single(ops, x, 0)
-    ref = blocks.TwoDotBlocks(ints, mps).sigma(x.cpu().numpy())
-    assert np.linalg.norm(s - ref) <= 1e-10 * np.linalg.norm(ref)
+@pytest.fixture(scope="module")
+def oracle_sigmas(probs):
+    out = []
+    for i, (ints, mps, ops, x) in enumerate(probs):
+        psi = x.cpu().numpy()
+        if i == DET:
+            ds = detci.DetSpace(ints, mps)
+            out.append(ds.sigma_rows(psi, np.arange(ds.n_psi))[0])
+        else:
+            out.append(blocks.TwoDotBlocks(ints, mps).sigma(psi))
+    return out
+
+
+def test_small_budget_still_matches_oracle(probs, oracle_sigmas):
+    for i, (ints, mps, ops, x) in enumerate(probs):
+        assert_close(single(ops, x, 0), oracle_sigmas[i], ops.blk_off, label=f"single {i}")
+
+
+@pytest.mark.parametrize("flags", [0, 1])   # graph + tuned, eager
+def test_every_batched_problem_matches_oracle(ctx, probs, oracle_sigmas, flags):
+    _, got = batched(ctx, probs, [p[3] for p in probs], 0, flags)
+    for i, (g, ref) in enumerate(zip(got, oracle_sigmas)):
+        assert_close(g, ref, probs[i][2].blk_off, label=f"batched {i} flags {flags}")
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])

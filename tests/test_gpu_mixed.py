@@ -116,3 +116,61 @@ def test_mixed_davidson_energy(ctx, prec):
     v = x.cpu().numpy()
     e_red = v @ gpu_sigma(ops, v, prec)
     print(f"prec={prec} reduced Rayleigh quotient error {e_red - efci:.3e} Eh")
+
+
+# Full-size reduced-precision sigma (K36 D3000 is the mixed-precision
+# workload; K73 D2000 the benchmark bond) against the FP64 GPU sigma, which
+# test_gpu_fullsize pins to the oracle at the same sizes.  Here a sigma
+# element accumulates up to ~1e5-1e6 products in FP32, so the sqrt(n) u
+# argument above would allow ~1e-4; the measured relative 2-norm errors are
+# far smaller (FP32 1.1e-6 / 1.3e-6, split-BF16 2.9e-6 / 2.8e-6 at K36 / K73,
+# about 20 u and 0.2 u_eff: the rounding errors of the FP32 tile sums are
+# themselves averaged by the binary64 accumulation across tasks).  The
+# tolerances are about 8x those measurements, so a change that loses a
+# power of two of accuracy anywhere fails.
+FULL = [(36, 36, 3000, 3), (73, 114, 2000, 5)]
+TOL_FULL = {FP32: 1e-5, BF16X3: 2.5e-5}
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("K,N,D,seed", FULL, ids=["K36_D3000", "K73_D2000"])
+def test_reduced_sigma_full_size(ctx, K, N, D, seed):
+    from parity import metrics
+    ints = synth.make_integrals(K, 1000 + seed)
+    mps = synth.make_mps(K, N // 2, N // 2, D, K // 2 - 1, 3000 + seed)
+    psi = synth.make_psi(mps, 2000 + seed)
+    print(f"K={K} D={D} building", flush=True)
+    ops = ctx.build_ops(ints, mps, x_budget=4 << 30)
+    s64 = gpu_sigma(ops, psi, 0)
+    for prec in (FP32, BF16X3):
+        g, e, b = metrics(gpu_sigma(ops, psi, prec), s64, ops.blk_off)
+        print(f"K={K} D={D} prec={prec} rel2={g:.3e} relmax={e:.3e} relblock={b:.3e}", flush=True)
+        assert g <= TOL_FULL[prec], (prec, g)
+    ops.destroy()
+
+
+@pytest.mark.timeout(900)
+def test_mixed_davidson_energy_k36(ctx):
+    # K=36, N=36, D=3000: the FP32 and split-BF16 Davidson energies against the
+    # FP64 Davidson energy from the same start, to 1e-6 Eh
+    import time
+
+    import torch
+    K, N, D, seed = 36, 36, 3000, 3
+    ints = synth.make_integrals(K, 1000 + seed)
+    mps = synth.make_mps(K, N // 2, N // 2, D, K // 2 - 1, 3000 + seed)
+    psi = synth.make_psi(mps, 2000 + seed)
+    print("K36 D3000 building", flush=True)
+    ops = ctx.build_ops(ints, mps)
+    res = {}
+    for prec in (0, BF16X3, FP32):
+        x = torch.from_numpy(psi).cuda()
+        t = time.time()
+        e, st = ops.davidson(x.data_ptr(), tol_residual=1e-5, max_iter=300, precision=prec)
+        res[prec] = e
+        print(f"K36 D3000 prec={prec} E={e:.10f} it={st['iterations']} fp64={st['sigma_fp64']} "
+              f"{time.time() - t:.1f} s", flush=True)
+        assert st["converged"]
+    for prec in (BF16X3, FP32):
+        assert abs(res[prec] - res[0]) <= 1e-6, (prec, res[prec] - res[0])
+    ops.destroy()

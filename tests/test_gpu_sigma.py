@@ -9,6 +9,7 @@ import pytest
 
 import synth
 from oracle import blocks, fock, solve
+from parity import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -64,9 +65,8 @@ def test_config1_sigma_vs_bruteforce(ctx):
     ints, mps, psi = problem(8, 4, 4, 64, 3, 1)
     ops = ctx.build_ops(ints, mps)
     s = gpu_sigma(ops, psi)
-    e0 = rel(s, fock.TwoDotFock(ints, mps).sigma(psi))
-    e1 = rel(s, blocks.TwoDotBlocks(ints, mps).sigma(psi))
-    assert e0 <= TOL and e1 <= TOL, (e0, e1)
+    assert_close(s, fock.TwoDotFock(ints, mps).sigma(psi), ops.blk_off, label="vs O0")
+    assert_close(s, blocks.TwoDotBlocks(ints, mps).sigma(psi), ops.blk_off, label="vs O1")
 
 
 @pytest.mark.parametrize("K,Na,Nb,D,k,seed", [
@@ -78,17 +78,16 @@ def test_config1_sigma_vs_bruteforce(ctx):
 ])
 def test_sigma_vs_renormalized_oracle(ctx, K, Na, Nb, D, k, seed):
     ints, mps, psi = problem(K, Na, Nb, D, k, seed)
-    ops = ctx.build_ops(ints, mps)
+    ops = ctx.build_ops(ints, mps, x_budget=1 << 20)   # small R-step scratch: several X chunks
     s = gpu_sigma(ops, psi)
-    err = rel(s, blocks.TwoDotBlocks(ints, mps).sigma(psi))
-    assert err <= TOL, err
+    print(f"K={K} D={D} n_psi={len(psi)} max sector {max(b[4] for b in synth.psi_block_list(mps))}")
+    assert_close(s, blocks.TwoDotBlocks(ints, mps).sigma(psi), ops.blk_off, label=f"K{K} D{D}")
 
 
 def test_sigma_with_core_energy(ctx):
     ints, mps, psi = problem(8, 4, 4, 32, 3, 7, ecore=3.7)
     ops = ctx.build_ops(ints, mps)
-    err = rel(gpu_sigma(ops, psi), blocks.TwoDotBlocks(ints, mps).sigma(psi))
-    assert err <= TOL, err
+    assert_close(gpu_sigma(ops, psi), blocks.TwoDotBlocks(ints, mps).sigma(psi), ops.blk_off, label="ecore")
 
 
 def test_diag_vs_oracle(ctx):
@@ -147,3 +146,23 @@ def test_config2_hermitian_deterministic(ctx):
     s3 = gpu_sigma(ops, 2 * x - 0.5 * y)
     lin = rel(s3, 2 * sx - 0.5 * sy)
     assert lin <= 1e-12, lin
+
+
+@pytest.mark.parametrize("K,Na,Nb,D,k,seed,dense", [
+    (8, 4, 4, 16, 3, 21, True),     # n_psi 576: the dense branch of eig_ref
+    (10, 5, 5, 40, 4, 22, False),   # the Lanczos (eigsh) branch
+])
+def test_truncated_davidson_vs_eig_ref(ctx, K, Na, Nb, D, k, seed, dense):
+    import torch
+    ints, mps, psi = problem(K, Na, Nb, D, k, seed)
+    ob = blocks.TwoDotBlocks(ints, mps)
+    n = len(psi)
+    eref, vref = solve.eig_ref(ob.sigma, n, dense_limit=n if dense else 0)
+    ops = ctx.build_ops(ints, mps)
+    x = torch.from_numpy(psi).cuda()
+    e, st = ops.davidson(x.data_ptr(), tol_residual=1e-8, max_iter=400)
+    v = x.cpu().numpy()
+    print(f"K={K} D={D} n={n} E={e:.12f} E_ref={eref:.12f} it={st['iterations']}")
+    assert st["converged"]
+    assert abs(e - eref) <= 1e-9
+    assert 1.0 - abs(v @ vref) <= 1e-8
