@@ -21,6 +21,13 @@
  *   - Every entry point that takes a context issues its GPU work on the
  *     context's HIP stream, in call order.  Calls that share a context must
  *     not run concurrently from several host threads.
+ *   - An operator handle (dmrg_ops) is not read-only: sigma, diag, Davidson
+ *     and the preconditioner calls reuse scratch it owns (the R-step buffers,
+ *     FP32 operator copies, work counters).  Calls on one handle are ordered
+ *     on the GPU even across contexts: a call on a stream other than the
+ *     handle's previous one first makes its stream wait for the previous
+ *     call's work.  Calls on one handle must still not be made concurrently
+ *     from several host threads.
  */
 #ifndef DMRG_H
 #define DMRG_H
@@ -185,11 +192,11 @@ int dmrg_profile(dmrg_ops* ops, int enable);
  * sigma are still binary64 buffers; the contraction runs in reduced precision
  * with FP32 accumulation.  Asynchronous on the context stream.  psi and sigma
  * must not overlap. */
-int dmrg_sigma(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi, double* sigma,
+int dmrg_sigma(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi, double* sigma,
                int precision);
 
 /* Diagonal H_ii of the two-dot Hamiltonian in the psi layout (device output). */
-int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag);
+int dmrg_diag(dmrg_ctx* ctx, dmrg_ops* ops, double* diag);
 
 /* sigma for nprob independent problems (each its own dmrg_ops, psi and sigma
  * device buffers, psi/sigma as in dmrg_sigma) in one fused launch sequence:
@@ -204,7 +211,7 @@ int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag);
  * call and calls with new pointers synchronise it). */
 #define DMRG_BATCH_EAGER 1
 #define DMRG_BATCH_NO_TUNE 2
-int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops,
+int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, dmrg_ops* const* ops,
                        const double* const* psi, double* const* sigma, int precision, int flags);
 
 /* Autotune the launch shapes of dmrg_sigma in one precision: every tile shape
@@ -230,7 +237,7 @@ int dmrg_launch_shape(dmrg_ops* ops, int precision, int tile, int64_t grid_per_x
 /* Lowest eigenpair.  psi (device, n_psi) holds the initial guess and receives
  * the normalised eigenvector; *energy its FP64 Rayleigh quotient (ecore
  * included).  Synchronous.  opts or stats may be NULL (defaults). */
-int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi,
+int dmrg_davidson(dmrg_ctx* ctx, dmrg_ops* ops, double* psi,
                   const dmrg_davidson_opts* opts, double* energy,
                   dmrg_davidson_stats* stats);
 void dmrg_davidson_default_opts(dmrg_davidson_opts* opts);
@@ -274,7 +281,7 @@ int dmrg_mlp_init(float* weights, uint64_t seed);
  * (which holds the Ritz vector) -- the direction the next correction has to
  * supply -- and s = <d,e>/<e,e> is the scale that best matches d.  Host outputs of capacity cap pairs: feat[cap][NFEAT], dcorr[cap],
  * target[cap]; *n_out receives the number written.  Synchronous. */
-int dmrg_mlp_collect(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi0, const double* psi_ref,
+int dmrg_mlp_collect(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi0, const double* psi_ref,
                      int max_iter, int per_iter, uint64_t seed, int64_t cap, float* feat,
                      float* dcorr, float* target, int64_t* n_out);
 
@@ -296,7 +303,7 @@ int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dco
 
 /* One preconditioner application on the device: t = g(f) * d for residual r
  * and diagonal diag (device, n_psi each) at Ritz value theta; weights host. */
-int dmrg_mlp_apply(dmrg_ctx* ctx, const dmrg_ops* ops, const float* weights, const double* r,
+int dmrg_mlp_apply(dmrg_ctx* ctx, dmrg_ops* ops, const float* weights, const double* r,
                    const double* diag, double theta, double* t);
 
 #ifdef __cplusplus

@@ -86,6 +86,7 @@ int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mp
     auto o = dmrg::build_ops(I, K, mps->n_alpha, mps->n_beta, mps->bond, mps->nsec, mps->sec_qn, mps->sec_dim,
                              mps->blk_off, mps->data, ctx->stream, opt);
     o->device = ctx->device;
+    o->end_call(ctx->stream);
     auto h = new dmrg_ops();
     h->p = std::move(o);
     *out = h;
@@ -153,25 +154,31 @@ int dmrg_profile(dmrg_ops* ops, int enable) {
   return DMRG_OK;
 }
 
-int dmrg_sigma(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi, double* sigma, int precision) {
+int dmrg_sigma(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi, double* sigma, int precision) {
   if (!ctx || !ops || !psi || !sigma) return DMRG_EINVAL;
   return guarded(ctx, [&] {
     DMRG_CHECK(precision >= 0 && precision <= 2, DMRG_EINVAL, "unknown precision");
     DMRG_CHECK(psi != sigma, DMRG_EINVAL, "psi and sigma must not alias");
-    dmrg::sigma_run(*ops->p, psi, sigma, precision, ctx->stream);
+    dmrg::Ops& O = *ops->p;
+    O.begin_call(ctx->stream);
+    dmrg::sigma_run(O, psi, sigma, precision, ctx->stream);
+    O.end_call(ctx->stream);
     return (int)DMRG_OK;
   });
 }
 
-int dmrg_diag(dmrg_ctx* ctx, const dmrg_ops* ops, double* diag) {
+int dmrg_diag(dmrg_ctx* ctx, dmrg_ops* ops, double* diag) {
   if (!ctx || !ops || !diag) return DMRG_EINVAL;
   return guarded(ctx, [&] {
-    dmrg::diag_run(*ops->p, diag, ctx->stream);
+    dmrg::Ops& O = *ops->p;
+    O.begin_call(ctx->stream);
+    dmrg::diag_run(O, diag, ctx->stream);
+    O.end_call(ctx->stream);
     return (int)DMRG_OK;
   });
 }
 
-int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops, const double* const* psi,
+int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, dmrg_ops* const* ops, const double* const* psi,
                        double* const* sigma, int precision, int flags) {
   if (!ctx || nprob < 0 || (nprob > 0 && (!ops || !psi || !sigma))) return DMRG_EINVAL;
   if (nprob == 0) return DMRG_OK;
@@ -190,12 +197,14 @@ int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, const dmrg_ops* const* ops, con
       ctx->batch.reset();
       ctx->batch = dmrg::build_batch(v, precision, ctx->stream);
     }
+    for (dmrg::Ops* o : v) o->begin_call(ctx->stream);
     dmrg::BatchPlan& B = *ctx->batch;
     if (!B.tuned && !(flags & DMRG_BATCH_NO_TUNE)) {
       B.bind(psi, sigma, ctx->stream);
       B.autotune(ctx->stream);
     }
     B.run(psi, sigma, !(flags & DMRG_BATCH_EAGER), ctx->stream);
+    for (dmrg::Ops* o : v) o->end_call(ctx->stream);
     return (int)DMRG_OK;
   });
 }
@@ -216,7 +225,9 @@ int dmrg_launch_shape(dmrg_ops* ops, int precision, int tile, int64_t grid_per_x
 int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_default, double* ms_tuned) {
   if (!ctx || !ops) return DMRG_EINVAL;
   return guarded(ctx, [&] {
+    ops->p->begin_call(ctx->stream);
     dmrg::sigma_autotune(*ops->p, precision, ctx->stream);
+    ops->p->end_call(ctx->stream);
     if (ms_default) *ms_default = ops->p->tune_ms_default[precision];
     if (ms_tuned) *ms_tuned = ops->p->tune_ms_best[precision];
     return (int)DMRG_OK;
@@ -242,7 +253,7 @@ void dmrg_davidson_default_opts(dmrg_davidson_opts* o) {
   o->e_tol = 1e-6;
 }
 
-int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi, const dmrg_davidson_opts* opts, double* energy,
+int dmrg_davidson(dmrg_ctx* ctx, dmrg_ops* ops, double* psi, const dmrg_davidson_opts* opts, double* energy,
                   dmrg_davidson_stats* stats) {
   if (!ctx || !ops || !psi || !energy) return DMRG_EINVAL;
   dmrg_davidson_opts o;
@@ -250,7 +261,12 @@ int dmrg_davidson(dmrg_ctx* ctx, const dmrg_ops* ops, double* psi, const dmrg_da
     o = *opts;
   else
     dmrg_davidson_default_opts(&o);
-  return guarded(ctx, [&] { return dmrg::davidson_run(*ops->p, psi, o, energy, stats, ctx->stream); });
+  return guarded(ctx, [&] {
+    ops->p->begin_call(ctx->stream);
+    int rc = dmrg::davidson_run(*ops->p, psi, o, energy, stats, ctx->stream);
+    ops->p->end_call(ctx->stream);
+    return rc;
+  });
 }
 
 int dmrg_mlp_nweights(void) { return dmrg::mlp_nweights(); }
@@ -261,14 +277,16 @@ int dmrg_mlp_init(float* weights, uint64_t seed) {
   return DMRG_OK;
 }
 
-int dmrg_mlp_collect(dmrg_ctx* ctx, const dmrg_ops* ops, const double* psi0, const double* psi_ref, int max_iter,
+int dmrg_mlp_collect(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi0, const double* psi_ref, int max_iter,
                      int per_iter, uint64_t seed, int64_t cap, float* feat, float* dcorr, float* target,
                      int64_t* n_out) {
   if (!ctx || !ops || !psi0 || !psi_ref || !feat || !dcorr || !target || !n_out) return DMRG_EINVAL;
   return guarded(ctx, [&] {
     DMRG_CHECK(max_iter > 0 && per_iter > 0 && cap >= 0, DMRG_EINVAL, "max_iter, per_iter > 0 and cap >= 0 needed");
+    ops->p->begin_call(ctx->stream);
     *n_out = dmrg::mlp_collect(*ops->p, psi0, psi_ref, max_iter, per_iter, seed, cap, feat, dcorr, target,
                                ctx->stream);
+    ops->p->end_call(ctx->stream);
     return (int)DMRG_OK;
   });
 }
@@ -284,11 +302,13 @@ int dmrg_mlp_train(dmrg_ctx* ctx, int64_t n, const float* feat, const float* dco
   });
 }
 
-int dmrg_mlp_apply(dmrg_ctx* ctx, const dmrg_ops* ops, const float* weights, const double* r, const double* diag,
+int dmrg_mlp_apply(dmrg_ctx* ctx, dmrg_ops* ops, const float* weights, const double* r, const double* diag,
                    double theta, double* t) {
   if (!ctx || !ops || !weights || !r || !diag || !t) return DMRG_EINVAL;
   return guarded(ctx, [&] {
+    ops->p->begin_call(ctx->stream);
     dmrg::mlp_apply_once(*ops->p, weights, r, diag, theta, t, ctx->stream);
+    ops->p->end_call(ctx->stream);
     return (int)DMRG_OK;
   });
 }

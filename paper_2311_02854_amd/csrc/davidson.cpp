@@ -26,8 +26,8 @@ struct DBuf {
   ~DBuf() { dev_free(p); }
 };
 
-double ddot(const double* x, const double* y, int64_t n, double* scratch, void* s) {
-  k_multidot(x, 0, 1, y, n, scratch, s);
+double ddot(const double* x, const double* y, int64_t n, double* scratch, double* part, void* s) {
+  k_multidot(x, 0, 1, y, n, scratch, part, s);
   double v;
   dev_d2h(&v, scratch, sizeof(double), s);
   return v;
@@ -44,13 +44,14 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
              "precond 1 needs mlp_weights");
   DMRG_CHECK(opt.precond_shift >= 0 && std::isfinite(opt.precond_shift), DMRG_EINVAL,
              "precond_shift must be finite and >= 0");
-  DBuf V((size_t)mmax * n), W((size_t)mmax * n), dg(n), x(n), hx(n), r(n), t(n), xp(n), hxp(n), sm(4 * 32 * 32 + 64);
+  DBuf V((size_t)mmax * n), W((size_t)mmax * n), dg(n), x(n), hx(n), r(n), t(n), xp(n), hxp(n), sm(4 * 32 * 32 + 64 + (size_t)MULTIDOT_PART * 32);
   double* dvals = sm.p;            // dots
   double* dG = sm.p + 64;          // projected matrix
   double* dw = dG + 32 * 32;       // eigenvalues
   double* dZ = dw + 32;            // eigenvectors
   double* dy = dZ + 32 * 32;       // coefficients
   double* dth = dy + 32;           // theta
+  double* dpart = dth + 64;        // partial sums of the dot products (MULTIDOT_PART x 32)
   diag_run(O, dg.p, stream);
   std::vector<double> G(32 * 32, 0.0), y(32, 0.0), yprev(32, 0.0), Z(32 * 32);
   int prec = opt.precision;
@@ -65,7 +66,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   auto Wp = [&](int j) { return W.p + (int64_t)j * n; };
 
   // v0 = psi / |psi|
-  double nrm = std::sqrt(ddot(psi, psi, n, dvals, stream));
+  double nrm = std::sqrt(ddot(psi, psi, n, dvals, dpart, stream));
   DMRG_CHECK(nrm > 0 && std::isfinite(nrm), DMRG_EINVAL, "initial vector is zero or not finite");
   k_copy(psi, Vp(0), n, stream);
   k_scale(Vp(0), 1.0 / nrm, n, stream);
@@ -81,7 +82,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
 
   auto rebuild_G = [&]() {  // full projected matrix of the current subspace
     for (int j = 0; j < m; ++j) {
-      k_multidot(V.p, n, m, Wp(j), n, dvals, stream);
+      k_multidot(V.p, n, m, Wp(j), n, dvals, dpart, stream);
       std::vector<double> col(m);
       dev_d2h(col.data(), dvals, sizeof(double) * m, stream);
       for (int i = 0; i < m; ++i) G[i * 32 + j] = col[i];
@@ -91,10 +92,10 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
   };
   auto orth_normalize = [&](double* v, int mcur) -> double {
     for (int pass = 0; pass < 2; ++pass) {
-      k_multidot(V.p, n, mcur, v, n, dvals, stream);
+      k_multidot(V.p, n, mcur, v, n, dvals, dpart, stream);
       k_sub_lincomb(V.p, n, mcur, dvals, n, v, stream);
     }
-    double nv = std::sqrt(ddot(v, v, n, dvals, stream));
+    double nv = std::sqrt(ddot(v, v, n, dvals, dpart, stream));
     if (nv > 0 && std::isfinite(nv)) k_scale(v, 1.0 / nv, n, stream);
     return nv;
   };
@@ -117,7 +118,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     k_lincomb(W.p, n, m, dy, n, hx.p, stream);
     k_copy(hx.p, r.p, n, stream);
     k_axpby(-theta, x.p, 1.0, r.p, n, stream);
-    rn = std::sqrt(ddot(r.p, r.p, n, dvals, stream));
+    rn = std::sqrt(ddot(r.p, r.p, n, dvals, dpart, stream));
     if (opt.trace && ntrace < opt.trace_cap) {
       double* row = opt.trace + 4 * (int64_t)ntrace++;
       row[0] = wall_seconds() - t_start;
@@ -154,7 +155,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
         k_lincomb(V.p, n, m, dy, n, xp.p, stream);
       }
       k_copy(x.p, Vp(0), n, stream);
-      double nx = std::sqrt(ddot(Vp(0), Vp(0), n, dvals, stream));
+      double nx = std::sqrt(ddot(Vp(0), Vp(0), n, dvals, dpart, stream));
       k_scale(Vp(0), 1.0 / nx, n, stream);
       int mnew = 1;
       if (have_prev) {
@@ -203,10 +204,10 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       k_copy(x.p, Vp(0), n, stream);
       k_copy(hx.p, Wp(0), n, stream);
       if (have_prev) {
-        double c = ddot(x.p, xp.p, n, dvals, stream);
+        double c = ddot(x.p, xp.p, n, dvals, dpart, stream);
         k_axpby(-c, x.p, 1.0, xp.p, n, stream);
         k_axpby(-c, hx.p, 1.0, hxp.p, n, stream);
-        double nx = std::sqrt(ddot(xp.p, xp.p, n, dvals, stream));
+        double nx = std::sqrt(ddot(xp.p, xp.p, n, dvals, dpart, stream));
         if (nx > 1e-3) {
           k_copy(xp.p, Vp(1), n, stream);
           k_copy(hxp.p, Wp(1), n, stream);
@@ -235,18 +236,18 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     if (prec == P_F64) ++iters64;
     ++m;
     // new column/row of the projected matrix
-    k_multidot(V.p, n, m, Wp(m - 1), n, dvals, stream);
+    k_multidot(V.p, n, m, Wp(m - 1), n, dvals, dpart, stream);
     std::vector<double> col(m);
     dev_d2h(col.data(), dvals, sizeof(double) * m, stream);
     for (int i = 0; i < m; ++i) G[i * 32 + (m - 1)] = G[(m - 1) * 32 + i] = col[i];
   }
   k_copy(x.p, psi, n, stream);
-  double nx = std::sqrt(ddot(psi, psi, n, dvals, stream));
+  double nx = std::sqrt(ddot(psi, psi, n, dvals, dpart, stream));
   k_scale(psi, 1.0 / nx, n, stream);
   if (prec != P_F64) {
     // stopped before the switch: report the FP64 Rayleigh quotient
     sig(psi, hx.p, P_F64);
-    theta = ddot(psi, hx.p, n, dvals, stream);
+    theta = ddot(psi, hx.p, n, dvals, dpart, stream);
     ++iters;
     ++iters64;
   }

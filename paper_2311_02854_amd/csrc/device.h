@@ -90,6 +90,7 @@ double wall_seconds();
 void* ev_create();
 void ev_destroy(void* ev);
 void ev_record(void* ev, void* stream);
+void stream_wait(void* stream, void* ev);   // later work on stream waits for ev
 float ev_elapsed_ms(void* a, void* b);   // both recorded and complete
 
 // streams and graphs: a non-blocking stream of default priority, stream
@@ -123,8 +124,12 @@ void k_d2f(const double* x, float* y, int64_t n, void* stream);
 void k_f2d(const float* x, double* y, int64_t n, void* stream);
 void k_axpby(double a, const double* x, double b, double* y, int64_t n, void* stream);  // y = a x + b y
 void k_copy(const double* x, double* y, int64_t n, void* stream);
-// out[i] = sum_j V[j*ld + k] * x[k] over k for j < m  (dots of m vectors with x); result on device
-void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, double* out, void* stream);
+// out[i] = sum_j V[j*ld + k] * x[k] over k for j < m  (dots of m vectors with x); result on device.
+// part: caller-owned device scratch of MULTIDOT_PART * m doubles for the fixed-order partial sums
+// (calls that may run concurrently need their own)
+constexpr int MULTIDOT_PART = 512;
+void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, double* out, double* part,
+                void* stream);
 // y[k] = sum_j c[j] V[j*ld + k]   (c on device)
 void k_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* stream);
 // y[k] -= sum_j c[j] V[j*ld + k]

@@ -9,6 +9,8 @@
 // is fixed, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <chrono>
 #include <cstdio>
 #include <string>
@@ -74,6 +76,7 @@ void ev_destroy(void* ev) {
   if (ev) (void)hipEventDestroy((hipEvent_t)ev);
 }
 void ev_record(void* ev, void* stream) { HIPCHK(hipEventRecord((hipEvent_t)ev, S(stream))); }
+void stream_wait(void* stream, void* ev) { HIPCHK(hipStreamWaitEvent(S(stream), (hipEvent_t)ev, 0)); }
 float ev_elapsed_ms(void* a, void* b) {
   float ms = 0;
   HIPCHK(hipEventSynchronize((hipEvent_t)b));
@@ -741,10 +744,21 @@ static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, c
 }
 
 // Workgroups of one GEMM kernel variant resident per compute unit.
+// Occupancy and CU counts are cached per device (devices may differ).
+constexpr int MAX_DEVICES = 64;
+static int current_device() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  DMRG_CHECK(dev >= 0 && dev < MAX_DEVICES, DMRG_EINVAL, "device index beyond the occupancy cache");
+  return dev;
+}
+
 template <class P>
 static int blocks_per_cu_of(int tile) {
-  static int cache[NTILE] = {0};
-  if (cache[tile] == 0) {
+  static std::atomic<int> cache[MAX_DEVICES][NTILE];
+  const int dev = current_device();
+  int v = cache[dev][tile].load(std::memory_order_relaxed);
+  if (v == 0) {
     const void* f = nullptr;
     switch (tile) {
       case TILE_32x32:
@@ -765,9 +779,10 @@ static int blocks_per_cu_of(int tile) {
     }
     int nb = 0;
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, NT, 0));
-    cache[tile] = nb > 0 ? nb : 1;
+    v = nb > 0 ? nb : 1;
+    cache[dev][tile].store(v, std::memory_order_relaxed);
   }
-  return cache[tile];
+  return v;
 }
 static int blocks_per_cu(int elem, int tile) {
   DMRG_CHECK(tile >= 0 && tile < NTILE, DMRG_EINVAL, "unknown GEMM tile shape");
@@ -776,12 +791,13 @@ static int blocks_per_cu(int elem, int tile) {
   return blocks_per_cu_of<PolBF3>(tile);
 }
 static int cu_count() {
-  static int n = 0;
+  static std::atomic<int> cache[MAX_DEVICES];
+  const int dev = current_device();
+  int n = cache[dev].load(std::memory_order_relaxed);
   if (n == 0) {
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
     if (n < NXCD) n = NXCD;
+    cache[dev].store(n, std::memory_order_relaxed);
   }
   return n;
 }
@@ -876,7 +892,7 @@ void k_scale(double* y, double sc, int64_t n, void* s) {
 }
 
 // Dots of m vectors with x: two passes (fixed-order partial sums) -> deterministic.
-constexpr int MD_CHUNKS = 512;
+constexpr int MD_CHUNKS = MULTIDOT_PART;
 __global__ void multidot_partial(const double* V, int64_t ld, const double* x, int64_t n, double* part) {
   const int j = blockIdx.y, c = blockIdx.x;
   const int64_t per = (n + MD_CHUNKS - 1) / MD_CHUNKS;
@@ -907,18 +923,12 @@ __global__ void multidot_final(const double* part, int m, double* out) {
   if (threadIdx.x == 0) out[j] = red[0];
 }
 
-static double* g_part = nullptr;
-static int g_part_m = 0;
-
-void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, double* out, void* s) {
+void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, double* out, double* part,
+                void* s) {
   if (m <= 0) return;
-  if (m > g_part_m) {
-    if (g_part) dev_free(g_part);
-    g_part = (double*)dev_alloc(sizeof(double) * MD_CHUNKS * (size_t)m);
-    g_part_m = m;
-  }
-  hipLaunchKernelGGL(multidot_partial, dim3(MD_CHUNKS, m), dim3(256), 0, S(s), V, ld, x, n, g_part);
-  hipLaunchKernelGGL(multidot_final, dim3(m), dim3(256), 0, S(s), g_part, m, out);
+  DMRG_CHECK(part != nullptr, DMRG_EINVAL, "k_multidot without partial-sum scratch");
+  hipLaunchKernelGGL(multidot_partial, dim3(MD_CHUNKS, m), dim3(256), 0, S(s), V, ld, x, n, part);
+  hipLaunchKernelGGL(multidot_final, dim3(m), dim3(256), 0, S(s), part, m, out);
   dev_check("k_multidot");
 }
 

@@ -30,8 +30,9 @@ struct DBufF {
   ~DBufF() { dev_free(p); }
 };
 
+// scratch: 1 + MULTIDOT_PART doubles (result, then the partial sums)
 double dot(const double* x, const double* y, int64_t n, double* scratch, void* s) {
-  k_multidot(x, 0, 1, y, n, scratch, s);
+  k_multidot(x, 0, 1, y, n, scratch, scratch + 1, s);
   double v;
   dev_d2h(&v, scratch, sizeof(double), s);
   return v;
@@ -112,7 +113,7 @@ int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_i
                     int64_t cap, float* feat, float* dcorr, float* target, void* stream) {
   mlp_prepare(O, stream);
   const int64_t n = O.npsi;
-  DBufD x0(n), e(n), d(n), sc(64), dots(64);
+  DBufD x0(n), e(n), d(n), sc(1 + MULTIDOT_PART), dots(64), part((size_t)MULTIDOT_PART * 64);
   DBufF ff((size_t)per_iter * NF), fd(per_iter), fy(per_iter);
   int64_t* didx = (int64_t*)dev_alloc(sizeof(int64_t) * std::max(1, per_iter));
   k_copy(psi0, x0.p, n, stream);
@@ -127,7 +128,7 @@ int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_i
     // two projection passes
     k_copy(psi_ref, e.p, n, stream);
     for (int pass = 0; pass < 2; ++pass) {
-      k_multidot(V, n, m_sub, e.p, n, dots.p, stream);
+      k_multidot(V, n, m_sub, e.p, n, dots.p, part.p, stream);
       k_sub_lincomb(V, n, m_sub, dots.p, n, e.p, stream);
     }
     k_precond_diag(r, diag, theta_dev, FLOOR, d.p, n, stream);

@@ -81,9 +81,21 @@ Mat16 ann(int d) { return tr(cre(d)); }
 int nelec(int e) { return SITE_QN[e / 4].n() + SITE_QN[e % 4].n(); }
 }  // namespace dot
 
+void Ops::begin_call(void* stream) {
+  if (used && stream != last_stream && order_ev) stream_wait(stream, order_ev);
+}
+
+void Ops::end_call(void* stream) {
+  if (!order_ev) order_ev = ev_create();
+  ev_record(order_ev, stream);
+  last_stream = stream;
+  used = true;
+}
+
 Ops::~Ops() {
   launches.clear();
   for (void* e : events) ev_destroy(e);
+  ev_destroy(order_ev);
   if (L) L->free_dev();
   if (R) R->free_dev();
   for (auto& g : extra) g->free_dev();

@@ -79,6 +79,15 @@ struct Ops {
   double prof_ms = 0;
   int64_t prof_launches = 0, prof_calls = 0;
 
+  // ordering across streams: the handle's scratch (R-step slots, FP32
+  // copies, unit counters) is reused by every call, so a call on a stream
+  // other than the last one waits for the last call's work first
+  void* order_ev = nullptr;
+  void* last_stream = nullptr;
+  bool used = false;
+  void begin_call(void* stream);
+  void end_call(void* stream);
+
   ~Ops();
   int find_block(int il, int e, int ir) const {
     return blk_index[((size_t)il * 16 + e) * Rb.nsec() + ir];

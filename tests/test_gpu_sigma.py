@@ -166,3 +166,63 @@ def test_truncated_davidson_vs_eig_ref(ctx, K, Na, Nb, D, k, seed, dense):
     assert st["converged"]
     assert abs(e - eref) <= 1e-9
     assert 1.0 - abs(v @ vref) <= 1e-8
+
+
+def test_two_contexts_run_concurrently(ctx):
+    # Davidson on two contexts with their own streams, from two host threads at
+    # once: each call owns its dot-product scratch, so both results equal,
+    # bit for bit, those of the same calls made one after the other
+    import threading
+
+    import torch
+    from paper_2311_02854_amd import Context
+    specs = [(8, 4, 4, 64, 3, 1), (10, 5, 5, 64, 4, 3)]
+    streams = [torch.cuda.Stream() for _ in specs]
+    ctxs = [Context(0, s.cuda_stream) for s in streams]
+    probs = [problem(*s) for s in specs]
+    opss = [c.build_ops(p[0], p[1]) for c, p in zip(ctxs, probs)]
+    ref = []
+    for ops, p in zip(opss, probs):
+        x = torch.from_numpy(p[2]).cuda()
+        torch.cuda.synchronize()
+        e, _ = ops.davidson(x.data_ptr(), tol_residual=1e-8, max_iter=200)
+        ref.append((e, x.cpu().numpy()))
+    xs = [torch.from_numpy(p[2]).cuda() for p in probs]
+    torch.cuda.synchronize()
+    out = [None, None]
+
+    def run(i):
+        out[i] = opss[i].davidson(xs[i].data_ptr(), tol_residual=1e-8, max_iter=200)[0]
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for i in range(2):
+        assert out[i] == ref[i][0]
+        assert np.array_equal(xs[i].cpu().numpy(), ref[i][1])
+
+
+def test_one_handle_on_two_streams(ctx):
+    # sigma with one operator handle issued on two contexts' streams back to
+    # back: the second call waits for the first (they share the handle's
+    # R-step scratch), so both equal the single-stream results
+    import ctypes
+
+    import torch
+    from paper_2311_02854_amd import Context
+    ints, mps, psi = problem(12, 6, 6, 200, 4, 6)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ca, cb = Context(0, sa.cuda_stream), Context(0, sb.cuda_stream)
+    ops = ca.build_ops(ints, mps, x_budget=1 << 20)
+    rng = np.random.default_rng(3)
+    x1, x2 = [torch.from_numpy(rng.normal(size=len(psi))).cuda() for _ in range(2)]
+    r1, r2 = gpu_sigma(ops, x1.cpu().numpy()), gpu_sigma(ops, x2.cpu().numpy())
+    y1, y2 = torch.full_like(x1, float("nan")), torch.full_like(x2, float("nan"))
+    torch.cuda.synchronize()
+    p = ctypes.c_void_p
+    assert ca.lib.dmrg_sigma(ca.h, ops.h, p(x1.data_ptr()), p(y1.data_ptr()), 0) == 0
+    assert cb.lib.dmrg_sigma(cb.h, ops.h, p(x2.data_ptr()), p(y2.data_ptr()), 0) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(y1.cpu().numpy(), r1) and np.array_equal(y2.cpu().numpy(), r2)
