@@ -198,6 +198,22 @@ int dmrg_sigma(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi, double* sigma,
 /* Diagonal H_ii of the two-dot Hamiltonian in the psi layout (device output). */
 int dmrg_diag(dmrg_ctx* ctx, dmrg_ops* ops, double* diag);
 
+/* dmrg_diag for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  It
+ * makes no device allocation: the gathered operator diagonals, the pointer
+ * table and the GEMM task lists live in a static 64 MiB device array of the
+ * library (one per GPU, set up by dmrg_create on that GPU and held until the
+ * process ends).  The members of each operator family are processed in
+ * chunks that fit it, so results equal dmrg_diag's to rounding (bit for bit
+ * when every family fits one chunk).  Limit: one member's diagonals,
+ * 8 * (left + right block dimension) bytes, plus a chunk's task list must fit
+ * in 60 MiB; otherwise DMRG_ENOMEM with a message, and diag is unspecified.
+ * The scratch keeps the last call's contents.  Calls on one GPU share it:
+ * the library serialises them within a process and each call is synchronous
+ * (returns when its work on the context stream is done); two processes on one
+ * GPU each have their own copy.  diag (device, n_psi) as in dmrg_diag. */
+int dmrg_diag_noalloc(dmrg_ctx* ctx, dmrg_ops* ops, double* diag);
+
 /* sigma for nprob independent problems (each its own dmrg_ops, psi and sigma
  * device buffers, psi/sigma as in dmrg_sigma) in one fused launch sequence:
  * launch j runs launch j of every problem's plan, with all problems' tiles in

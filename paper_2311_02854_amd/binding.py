@@ -19,7 +19,7 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ESHAPE", -3: "DMRG_ENOMEM",
           -5: "DMRG_ENOCONV", -6: "DMRG_EINTERNAL"}
 
 EXPORTS = ["dmrg_create", "dmrg_destroy", "dmrg_last_error", "dmrg_build_ops", "dmrg_ops_destroy",
-           "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_sigma_batched",
+           "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_diag_noalloc", "dmrg_sigma_batched",
            "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile", "dmrg_mlp_nweights",
            "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply", "dmrg_autotune",
            "dmrg_launch_shape"]
@@ -87,6 +87,7 @@ def load(path=None):
     lib.dmrg_ops_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.dmrg_sigma.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.dmrg_diag.argtypes = [vp, vp, vp]
+    lib.dmrg_diag_noalloc.argtypes = [vp, vp, vp]
     lib.dmrg_sigma_batched.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_int]
     lib.dmrg_autotune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.dmrg_launch_shape.argtypes = [vp, C.c_int, C.c_int, C.c_int64]
@@ -202,6 +203,10 @@ class Ops:
 
     def diag(self, out_ptr):
         self.ctx._check(self.ctx.lib.dmrg_diag(self.ctx.h, self.h, C.c_void_p(out_ptr)))
+
+    def diag_noalloc(self, out_ptr):
+        """diag(H) with the library's static scratch instead of allocations."""
+        self.ctx._check(self.ctx.lib.dmrg_diag_noalloc(self.ctx.h, self.h, C.c_void_p(out_ptr)))
 
     def davidson(self, psi_ptr, trace=0, **kw):
         """Lowest eigenpair in place; trace=N also returns the first N per-iteration rows

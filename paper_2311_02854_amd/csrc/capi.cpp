@@ -4,6 +4,7 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "../../include/dmrg.h"
@@ -51,6 +52,7 @@ int dmrg_create(dmrg_ctx** ctx, int device, void* hip_stream) {
   c->stream = hip_stream;
   int rc = guarded(c, [&] {
     dmrg::dev_set(device);
+    dmrg::scratch_init(device);  // the static scratch of dmrg_diag_noalloc on this device
     return (int)DMRG_OK;
   });
   if (rc != DMRG_OK) {
@@ -173,6 +175,21 @@ int dmrg_diag(dmrg_ctx* ctx, dmrg_ops* ops, double* diag) {
     dmrg::Ops& O = *ops->p;
     O.begin_call(ctx->stream);
     dmrg::diag_run(O, diag, ctx->stream);
+    O.end_call(ctx->stream);
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_diag_noalloc(dmrg_ctx* ctx, dmrg_ops* ops, double* diag) {
+  if (!ctx || !ops || !diag) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    // calls on one device share its static scratch: one at a time per process
+    static std::mutex mu[64];
+    DMRG_CHECK(ctx->device >= 0 && ctx->device < 64, DMRG_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu[ctx->device]);
+    dmrg::Ops& O = *ops->p;
+    O.begin_call(ctx->stream);
+    dmrg::diag_run_noalloc(O, diag, ctx->stream, dmrg::scratch_get(ctx->device), dmrg::scratch_bytes());
     O.end_call(ctx->stream);
     return (int)DMRG_OK;
   });

@@ -80,6 +80,12 @@ enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
 
 // --- runtime -------------------------------------------------------------
 void dev_set(int device);
+// Static device scratch of the allocation-free entry points: a file-scope
+// __device__ array of scratch_bytes() on every device.  scratch_init looks its
+// address up on `device` (which must be current) once; scratch_get returns it.
+size_t scratch_bytes();
+void scratch_init(int device);
+void* scratch_get(int device);
 void* dev_alloc(size_t bytes);          // zero-filled; throws Error(ENOMEM)
 void dev_free(void* p);
 void dev_h2d(void* dst, const void* src, size_t bytes);            // synchronous

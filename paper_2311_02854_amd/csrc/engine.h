@@ -51,6 +51,21 @@ class DevTable {
   bool dirty_ = true;
 };
 
+// Bump allocator over caller-provided device memory: places the arrays of a
+// task list without allocating (the allocation-free entry points).
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes) {
+    const size_t off = (used + 255) & ~size_t(255);
+    DMRG_CHECK(off + bytes <= cap, DMRG_ENOMEM,
+               "static scratch too small: needs more than its " + std::to_string(cap) + " bytes");
+    used = off + bytes;
+    return base + off;
+  }
+  void reset() { used = 0; }
+};
+
 // A list of GEMM tasks executed by one gemm_launch.  The host list is tile
 // independent; upload(tile) counts the tasks' tiles for one workgroup tile
 // shape, splits them into pieces and assigns the pieces to XCDs.  One device
@@ -222,25 +237,33 @@ class GemmList {
   }
 
   // Count tiles for shape tl, split tasks into job-range pieces, assign them
-  // to XCDs (longest processing time first) and upload the per-XCD lists.
-  void upload(int tl) {
+  // to XCDs (longest processing time first) and upload the per-XCD lists:
+  // into fresh device allocations, or into `arena` (nothing is allocated;
+  // the lists then live as long as the arena's memory is left alone).
+  void upload(int tl, Arena* arena = nullptr) {
     DMRG_CHECK(tl >= 0 && tl < NTILE, DMRG_EINVAL, "unknown tile shape");
     free_dev(dev_[tl]);
     if (tasks.empty()) return;
     Dev& D = dev_[tl];
+    D.external = arena != nullptr;
+    auto alloc = [&](size_t b) -> void* { return arena ? arena->take(b) : dev_alloc(b); };
     std::vector<GTask> src;
     std::vector<GContrib> cx;
     const GContrib* cs = contribs.data();
     if (tl == TILE_EDGE) {
       split_edges(src, cx);
       cs = cx.data();
-      D.contribs = (GContrib*)dev_alloc((cx.size() + 1) * sizeof(GContrib));
+      D.contribs = (GContrib*)alloc((cx.size() + 1) * sizeof(GContrib));
       if (!cx.empty()) dev_h2d(D.contribs, cx.data(), cx.size() * sizeof(GContrib));
       D.ncontribs = cx.size();
     } else {
       src = tasks;
       for (GTask& g : src) g.shape = tl;
-      if (!dcontribs_) {
+      if (arena) {  // own copy of the contributions, in the arena
+        D.contribs = (GContrib*)alloc((contribs.size() + 1) * sizeof(GContrib));
+        if (!contribs.empty()) dev_h2d(D.contribs, contribs.data(), contribs.size() * sizeof(GContrib));
+        D.ncontribs = contribs.size();
+      } else if (!dcontribs_) {
         dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
         if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
         ncontribs_dev_ = contribs.size();
@@ -321,9 +344,9 @@ class GemmList {
       units.push_back(jb);
       D.map.nunits[x] = (int64_t)units.size() - 1 - D.map.unit_begin[x];
     }
-    D.units = (int64_t*)dev_alloc(units.size() * sizeof(int64_t));
+    D.units = (int64_t*)alloc(units.size() * sizeof(int64_t));
     dev_h2d(D.units, units.data(), units.size() * sizeof(int64_t));
-    D.counters = (unsigned*)dev_alloc(64 * NXCD * sizeof(unsigned));
+    D.counters = (unsigned*)alloc(64 * NXCD * sizeof(unsigned));
     D.map.units = D.units;
     D.map.counters = D.counters;
     D.map.task_begin[NXCD] = (int)dev.size();
@@ -342,9 +365,9 @@ class GemmList {
       }
     }
     D.map.bucket_begin[NXCD] = (int)bucket.size();
-    D.bucket = (int*)dev_alloc(std::max<size_t>(1, bucket.size()) * sizeof(int));
+    D.bucket = (int*)alloc(std::max<size_t>(1, bucket.size()) * sizeof(int));
     dev_h2d(D.bucket, bucket.data(), bucket.size() * sizeof(int));
-    D.tasks = (GTask*)dev_alloc(dev.size() * sizeof(GTask));
+    D.tasks = (GTask*)alloc(dev.size() * sizeof(GTask));
     dev_h2d(D.tasks, dev.data(), dev.size() * sizeof(GTask));
     D.ntasks = (int)dev.size();
   }
@@ -353,10 +376,14 @@ class GemmList {
   void run(DevTable& tab, const void* p0, void* p1, int elem, void* stream) { run_tile(tile, tab, p0, p1, elem, stream); }
   void run_tile(int tl, DevTable& tab, const void* p0, void* p1, int elem, void* stream) {
     if (!dev_[tl].tasks) upload(tl);
+    run_uploaded(tl, tab.device(), p0, p1, elem, stream);
+  }
+  // launch the lists uploaded for shape tl with a device pointer table
+  void run_uploaded(int tl, void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
     const Dev& D = dev_[tl];
     if (D.ntasks == 0) return;
-    gemm_launch(D.tasks, D.ntasks, D.map, D.contribs ? D.contribs : dcontribs_, D.bucket, tab.device(), p0, p1,
-                elem, tl, grid_per_xcd, stream);
+    gemm_launch(D.tasks, D.ntasks, D.map, D.contribs ? D.contribs : dcontribs_, D.bucket, table_dev, p0, p1, elem,
+                tl, grid_per_xcd, stream);
   }
   void release() {
     for (int t = 0; t < NTILE; ++t) free_dev(dev_[t]);
@@ -389,8 +416,13 @@ class GemmList {
     size_t ncontribs = 0;
     XcdMap map{};
     int ntasks = 0;
+    bool external = false;         // placed in an Arena: not freed here
   };
   static void free_dev(Dev& d) {
+    if (d.external) {
+      d = Dev{};
+      return;
+    }
     dev_free(d.tasks);
     dev_free(d.bucket);
     dev_free(d.contribs);

@@ -31,8 +31,37 @@ namespace dmrg {
 
 static inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+constexpr int MAX_DEVICES = 64;
+
 // ---------------------------------------------------------------- runtime
 void dev_set(int device) { HIPCHK(hipSetDevice(device)); }
+
+// Static scratch of the allocation-free entry points (each device holds its
+// own copy until the process ends).  In host code `scratch` is only a
+// stand-in for the device symbol: its device address comes from
+// hipGetSymbolAddress, per device, and is the only form passed to kernels or
+// copies.
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::atomic<void*> g_scratch[MAX_DEVICES];
+
+size_t scratch_bytes() { return SCRATCH_BYTES; }
+
+void scratch_init(int device) {
+  DMRG_CHECK(device >= 0 && device < MAX_DEVICES, DMRG_EINVAL, "device index beyond the scratch table");
+  if (g_scratch[device].load(std::memory_order_acquire)) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  DMRG_CHECK(p != nullptr, DMRG_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+  g_scratch[device].store(p, std::memory_order_release);
+}
+
+void* scratch_get(int device) {
+  DMRG_CHECK(device >= 0 && device < MAX_DEVICES, DMRG_EINVAL, "device index beyond the scratch table");
+  void* p = g_scratch[device].load(std::memory_order_acquire);
+  DMRG_CHECK(p != nullptr, DMRG_EINTERNAL, "static scratch not set up on this device (no context created on it)");
+  return p;
+}
 
 void* dev_alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -745,7 +774,6 @@ static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, c
 
 // Workgroups of one GEMM kernel variant resident per compute unit.
 // Occupancy and CU counts are cached per device (devices may differ).
-constexpr int MAX_DEVICES = 64;
 static int current_device() {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));

@@ -1041,6 +1041,90 @@ void diag_run(Ops& O, double* diag, void* stream) {
   }
 }
 
+// The same sum as diag_run, for callers that cannot allocate: the members of
+// a family are taken in chunks whose diagonals fit the scratch next to the
+// chunk's task list, and each chunk adds its part to diag (binary64).  A
+// family that fits in one chunk gives bit-identical results; with several
+// chunks the partial sums are rounded once more per chunk.
+void diag_run_noalloc(Ops& O, double* diag, void* stream, void* scratch, size_t cap) {
+  constexpr size_t TASKLIST_RESERVE = size_t(4) << 20;  // task list, buckets, units of one chunk
+  k_fill(diag, 0.0, O.npsi, stream);
+  const int64_t nL = O.Lb.total, nR = O.Rb.total;
+  auto diag_meta = [](const Group& g, const Basis& B, std::vector<int64_t>& meta) {
+    meta.clear();
+    for (int bk = 0; bk < g.lay.nblk(); ++bk) {
+      if (g.lay.bra[bk] != g.lay.ket[bk]) continue;
+      int s = g.lay.ket[bk];
+      meta.push_back(g.lay.off[bk]);
+      meta.push_back(B.dim[s]);
+      meta.push_back(B.off[s]);
+    }
+  };
+  Arena A;
+  A.base = (char*)scratch;
+  A.cap = cap;
+  std::vector<int64_t> metaL, metaR;
+  for (const SFam& f : O.fams) {
+    bool dz = true;
+    if (f.L && !(f.L->dq == QN(0, 0))) dz = false;
+    if (f.R && !(f.R->dq == QN(0, 0))) dz = false;
+    if (!dz) continue;
+    bool anyd = false;
+    for (int e = 0; e < 16; ++e) anyd |= f.D[e * 16 + e] != 0.0;
+    if (!anyd) continue;
+    if (f.L) diag_meta(*f.L, O.Lb, metaL);
+    if (f.R) diag_meta(*f.R, O.Rb, metaR);
+    const size_t fixed = 4 * sizeof(void*) + (metaL.size() + metaR.size()) * sizeof(int64_t) + 4 * 256 +
+                         TASKLIST_RESERVE;
+    const size_t per_member = (size_t)(nL + nR) * sizeof(double);
+    DMRG_CHECK(cap > fixed + per_member + 512, DMRG_ENOMEM,
+               "diag without allocation: one member's diagonals (" + std::to_string(per_member) +
+                   " bytes) and a chunk's task list do not fit the " + std::to_string(cap) + "-byte static scratch");
+    int64_t chunk = (int64_t)((cap - fixed - 512) / per_member);
+    if (chunk >= 32) chunk -= chunk % 32;  // whole k tiles per chunk
+    for (int64_t t0 = 0; t0 < f.count; t0 += chunk) {
+      const int c = (int)std::min<int64_t>(chunk, f.count - t0);
+      dev_sync(stream);  // the previous chunk's kernels no longer read the scratch
+      A.reset();
+      void** dtab = (void**)A.take(4 * sizeof(void*));
+      double* dL = (double*)A.take(sizeof(double) * (size_t)c * nL);
+      double* dR = (double*)A.take(sizeof(double) * (size_t)c * nR);
+      void* tab_h[4] = {nullptr, nullptr, dL, dR};
+      dev_h2d(dtab, tab_h, sizeof tab_h);
+      if (f.L) {
+        int64_t* dm = (int64_t*)A.take(sizeof(int64_t) * std::max<size_t>(1, metaL.size()));
+        dev_h2d(dm, metaL.data(), metaL.size() * sizeof(int64_t));
+        k_gather_diag(f.L->dev + (int64_t)(f.Lbase + t0) * f.L->stride(), dm, (int)metaL.size() / 3,
+                      f.L->stride(), nL, c, dL, stream);
+      } else {
+        k_fill(dL, 1.0, (int64_t)c * nL, stream);
+      }
+      if (f.R) {
+        int64_t* dm = (int64_t*)A.take(sizeof(int64_t) * std::max<size_t>(1, metaR.size()));
+        dev_h2d(dm, metaR.data(), metaR.size() * sizeof(int64_t));
+        k_gather_diag(f.R->dev + (int64_t)(f.Rbase + t0) * f.R->stride(), dm, (int)metaR.size() / 3,
+                      f.R->stride(), nR, c, dR, stream);
+      } else {
+        k_fill(dR, 1.0, (int64_t)c * nR, stream);
+      }
+      GemmList gl;
+      for (const PsiBlk& b : O.blocks) {
+        double dv = f.D[b.e * 16 + b.e];
+        if (dv == 0.0) continue;
+        int zp = f.piD * O.Lb.qn[b.il].n() + f.piR * (O.Lb.qn[b.il].n() + dot::nelec(b.e));
+        double zeta = (zp & 1) ? -1.0 : 1.0;
+        gl.begin(b.dl, b.dr, 1, 1, b.off, b.dr, 0, true);
+        gl.add(make_contrib(c, GF_TRANS_A, 2, O.Lb.off[b.il], (int)nL, 3, O.Rb.off[b.ir], (int)nR,
+                            f.coef * dv * zeta));
+        gl.end();
+      }
+      gl.upload(TILE_64x64, &A);
+      gl.run_uploaded(TILE_64x64, dtab, nullptr, diag, P_F64, stream);
+    }
+  }
+  dev_sync(stream);
+}
+
 void make_reduced_copies(Ops& O, void* stream) {
   if (O.tab32) return;
   auto t32 = std::make_unique<DevTable>();

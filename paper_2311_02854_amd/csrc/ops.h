@@ -115,6 +115,11 @@ void autotune_launches(size_t nl, const std::function<void(const std::vector<int
                                                            std::vector<double>&)>& run_all,
                        std::vector<int>& tiles, std::vector<int64_t>& grids, double& ms_default, double& ms_best);
 void diag_run(Ops& ops, double* diag, void* stream);
+// diag(H) without allocating: operator diagonals, pointer table and GEMM task
+// lists live in `scratch` (cap bytes of device memory), members in chunks that
+// fit it.  Synchronous.  Throws ENOMEM if one member's diagonals and the task
+// list of one chunk do not fit.
+void diag_run_noalloc(Ops& ops, double* diag, void* stream, void* scratch, size_t cap);
 // FP32 copies of the sigma operators (idempotent; synchronous)
 void make_reduced_copies(Ops& ops, void* stream);
 

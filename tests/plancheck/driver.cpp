@@ -7,10 +7,11 @@
 // with a second copy of the problem, the fused two-problem sigma.  The
 // device layer checks every launch's addressing; this program only drives it.
 //
-//   plancheck INPUT X_BUDGET_BYTES full|short [batched]
+//   plancheck INPUT X_BUDGET_BYTES full|short [batched|noalloc_fails]
 // full: sigma with every launch shape; short: the 64x64 and mixed shapes with
 // one workgroup per job and dynamic units only (the other shapes share their
-// addressing code); batched: also the fused two-problem sigma
+// addressing code); batched: also the fused two-problem sigma; noalloc_fails:
+// dmrg_diag_noalloc must refuse (run with a static scratch set too small)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -23,6 +24,7 @@
 
 namespace dmrg {
 void plancheck_report();
+int64_t plancheck_alloc_count();
 }
 
 template <typename T>
@@ -110,6 +112,7 @@ int main(int argc, char** argv) {
   const size_t x_budget = std::strtoull(argv[2], nullptr, 10);
   const bool quick = argc > 3 && std::string(argv[3]) == "short";
   const bool batched = argc > 4 && std::string(argv[4]) == "batched";
+  const bool expect_noalloc_fail = argc > 4 && std::string(argv[4]) == "noalloc_fails";
   auto hdr = rd<int64_t>(f, 6);  // K, Na, Nb, bond, total sectors, blocks
   const int K = (int)hdr[0];
   auto nsec = rd<int>(f, (size_t)K + 1);
@@ -142,6 +145,24 @@ int main(int argc, char** argv) {
         ok(dmrg_sigma(ctx, ops, psi, sig, prec), ctx, "sigma");
       }
   ok(dmrg_diag(ctx, ops, sig), ctx, "diag");
+  {
+    // the allocation-free diag: no dev_alloc at all, every launch checked
+    const int64_t before = dmrg::plancheck_alloc_count();
+    const int rc = dmrg_diag_noalloc(ctx, ops, sig);
+    if (expect_noalloc_fail) {
+      if (rc != DMRG_ENOMEM) {
+        std::fprintf(stderr, "diag_noalloc with a small scratch returned %d, not DMRG_ENOMEM\n", rc);
+        return 1;
+      }
+      std::printf("diag_noalloc refused: %s\n", dmrg_last_error(ctx));
+    } else {
+      ok(rc, ctx, "diag_noalloc");
+    }
+    if (dmrg::plancheck_alloc_count() != before) {
+      std::fprintf(stderr, "diag_noalloc allocated device memory\n");
+      return 1;
+    }
+  }
   if (batched) {
     dmrg_ops* ops2 = nullptr;
     ok(dmrg_build_ops(ctx, &I, &M, &bo, &ops2), ctx, "build_ops (second)");

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -87,14 +88,36 @@ size_t count_of(const void* p, size_t elem) {
 }  // namespace
 
 void plancheck_report() {
-  std::printf("plancheck: %lld launches, %lld tasks, %lld contribution checks, %lld jobs, %zu live allocations\n",
+  std::printf("plancheck: %lld launches, %lld tasks, %lld contribution checks, %lld jobs, %zu live allocations "
+              "(the static scratch included)\n",
               (long long)g_stats.launches, (long long)g_stats.tasks, (long long)g_stats.contrib_checks,
               (long long)g_stats.jobs, g_alloc.size());
 }
 
 void dev_set(int) {}
 
+int64_t g_nalloc = 0;
+int64_t plancheck_alloc_count() { return g_nalloc; }
+
+// the static scratch: one fake allocation, of PLANCHECK_SCRATCH_BYTES if set
+static void* g_scratch = nullptr;
+size_t scratch_bytes() {
+  const char* e = std::getenv("PLANCHECK_SCRATCH_BYTES");
+  return e ? (size_t)std::strtoull(e, nullptr, 10) : (size_t(64) << 20);
+}
+void scratch_init(int) {
+  if (!g_scratch) {
+    g_scratch = dev_alloc(scratch_bytes());
+    --g_nalloc;  // set-up, not a call's allocation
+  }
+}
+void* scratch_get(int) {
+  if (!g_scratch) fail("static scratch used before set-up");
+  return g_scratch;
+}
+
 void* dev_alloc(size_t bytes) {
+  ++g_nalloc;
   const uint64_t a = g_next;
   const uint64_t sz = bytes ? bytes : 1;
   g_next += ((sz + 255) & ~uint64_t(255)) + GAP;

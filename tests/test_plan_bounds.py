@@ -54,9 +54,11 @@ def write_problem(path, K, Na, Nb, D, k, seed):
         ints["eri"].astype(np.float64).tofile(f)
 
 
-def run(exe, *args):
+def run(exe, *args, scratch=None):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    if scratch is not None:
+        env["PLANCHECK_SCRATCH_BYTES"] = str(scratch)
     r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=1200, env=env)
     print(r.stdout[-2000:], r.stderr[-4000:])
     return r
@@ -80,3 +82,18 @@ def test_full_size_plans_stay_in_bounds(exe, tmp_path, K, N, D, seed, xbudget, m
     r = run(exe, path, str(xbudget), *mode)
     assert r.returncode == 0, r.stderr[-4000:]
     assert "PLANCHECK OK" in r.stdout
+
+
+@pytest.mark.parametrize("scratch,expect", [(5 << 20, "ok"), (4 << 20, "refused")])
+def test_diag_noalloc_chunks_and_limit(exe, tmp_path, scratch, expect):
+    # dmrg_diag_noalloc with a 5 MiB static scratch (K24 D1000: members in
+    # many chunks, no allocation, every launch in bounds) and with 4 MiB (its
+    # task-list reserve alone fills it: refused with DMRG_ENOMEM)
+    path = str(tmp_path / "problem.bin")
+    write_problem(path, 24, 12, 12, 1000, 11, 2)
+    mode = ("short",) if expect == "ok" else ("short", "noalloc_fails")
+    r = run(exe, path, str(64 << 20), *mode, scratch=scratch)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert "PLANCHECK OK" in r.stdout
+    if expect == "refused":
+        assert "diag_noalloc refused" in r.stdout and "static scratch" in r.stdout
