@@ -325,6 +325,10 @@ def main():
                     help="arithmetic of the sigma contraction (psi and sigma stay binary64)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="launch every sigma GEMM with this mode (0-3 uniform tiles, 4 mixed 64/32 strips) "
+                         "instead of autotuning")
+    ap.add_argument("--grid", type=int, default=0, help="grid mode with --tile (0 one workgroup per job, -1 dynamic)")
     ap.add_argument("--x-budget-gb", type=float, default=0.0,
                     help="R-step scratch per slot in GB (0: library default)")
     ap.add_argument("--no-davidson", action="store_true",
@@ -376,7 +380,10 @@ def main():
         log("[bench] copy probe: 3 x 1 GiB device-to-device copies done")
     prec = PREC_ID[args.precision]
     tune = None
-    if not args.no_tune:
+    if args.tile is not None:
+        ops.launch_shape(prec, args.tile, args.grid)
+        tune = {"fixed_tile": args.tile, "grid": args.grid}
+    elif not args.no_tune:
         t0 = time.time()
         ms0, ms1 = ops.autotune(prec)
         tune = {"ms_default_shapes": ms0, "ms_tuned": ms1, "tune_s": time.time() - t0}

@@ -43,11 +43,11 @@ def ctx():
     return gpu_context(0)
 
 
-def gpu_sigma(ops, psi):
+def gpu_sigma(ops, psi, prec=0):
     import torch
     x = torch.from_numpy(np.ascontiguousarray(psi)).cuda()
     y = torch.full_like(x, float("nan"))
-    ops.sigma(x.data_ptr(), y.data_ptr())
+    ops.sigma(x.data_ptr(), y.data_ptr(), prec)
     torch.cuda.synchronize()
     out = y.cpu().numpy()
     del x, y
@@ -164,6 +164,17 @@ def test_wide_sectors_vs_o2(ctx):
     assert max(b[4] for b in ds.blocks) > 128
     ops = ctx.build_ops(ints, mps, x_budget=1 << 20)
     s = gpu_sigma(ops, psi)
+    # every launch mode (uniform 64/32 tiles, mixed 64/32 strips) and grid
+    # gives the same sigma bit for bit: each output element accumulates the
+    # same k sequence
+    for prec in (0, 1, 2):
+        ref = gpu_sigma(ops, psi, prec)
+        for tile in range(5):
+            for grid in (0, -1):
+                ops.launch_shape(prec, tile, grid)
+                got = gpu_sigma(ops, psi, prec)
+                assert np.array_equal(got, ref), (prec, tile, grid, np.abs(got - ref).max())
+        ops.launch_shape(prec, 0, 0)
     release(ops)
     rng = np.random.default_rng(seed)
     rows = []
