@@ -334,6 +334,8 @@ def main():
     ap.add_argument("--no-davidson", action="store_true",
                     help="skip the Davidson time-to-1e-6 Eh leg (plain FP64 + diagonal vs shifted, split-BF16, learned)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured DGEMM / copy / batched peaks")
+    ap.add_argument("--build-only", action="store_true",
+                    help="only build the operators (dmrg_build_ops) and print its wall time (for profiling)")
     ap.add_argument("--mixed", action="store_true",
                     help="also report FP32 / split-BF16 sigma and energy errors (always on for --config 3)")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_02854_amd", "data", "precond_mlp.npy"),
@@ -368,6 +370,11 @@ def main():
     st = ops.stats()
     log(f"[bench] build_ops {t_build:.1f} s ({st['build_flops'] / 1e12:.1f} TFLOP renormalization), "
         f"sigma plan {st['flops_sigma'] / 1e12:.3f} TFLOP/call, ops {st['op_bytes'] / 1e9:.1f} GB")
+    if args.build_only:
+        print(json.dumps({"build_ops_s": t_build, "build_tflop": st["build_flops"] / 1e12,
+                          "build_tflops_per_s": st["build_flops"] / t_build / 1e12,
+                          "operator_GB": st["op_bytes"] / 1e9}), flush=True)
+        return
     x = torch.from_numpy(psi).cuda()
     y = torch.empty_like(x)
     if args.copy_probe:

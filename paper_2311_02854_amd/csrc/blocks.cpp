@@ -73,13 +73,15 @@ int nelec(int n) { return SITE_QN[n].n(); }
 }  // namespace site
 
 // ------------------------------------------------------------------ groups
-void Group::alloc(DevTable& tab) {
+void Group::alloc(DevTable& tab, void* stream, DeviceArena* arena) {
   size_t cnt = (size_t)std::max<int64_t>(1, (int64_t)n() * lay.size);
-  dev = (double*)dev_alloc(cnt * sizeof(double));
+  dev = (double*)(arena ? arena->take(cnt * sizeof(double)) : dev_alloc_nozero(cnt * sizeof(double)));
+  in_arena = arena != nullptr;
+  k_zero_bytes(dev, cnt * sizeof(double), stream);
   buf = tab.add(dev);
 }
 void Group::free_dev() {
-  dev_free(dev);
+  if (!in_arena) dev_free(dev);
   dev = nullptr;
   dev_free(dev32);
   dev32 = nullptr;
@@ -94,8 +96,8 @@ int Block::member(int gid, OpKey k) const {
 
 void Builder::run(GemmList& gl) {
   if (gl.empty()) return;
-  gl.upload();
-  gl.run(tab, nullptr, nullptr, P_F64, stream);
+  gl.upload(gl.tile, nullptr, ring.get());
+  gl.run_uploaded(gl.tile, tab.device(*ring), nullptr, nullptr, P_F64, stream);
   st.flops += gl.flops;
   st.ngemm += gl.ngemm;
 }
@@ -121,25 +123,25 @@ std::unique_ptr<Block> Builder::vacuum(bool left) {
     B->g[G_SB].names.push_back({'S', 2 * i + 1, -1});
   }
   B->g[G_H].names.push_back({'H', -1, -1});
-  for (auto& x : B->g) x.alloc(tab);  // zero-filled: S = 0, H = 0 on the empty block
+  for (auto& x : B->g) x.alloc(tab, stream);  // zero-filled: S = 0, H = 0 on the empty block
   return B;
 }
 
 std::unique_ptr<Group> Builder::combine(const Group& src, const std::vector<std::vector<double>>& coef,
-                                        std::vector<OpKey> names) {
+                                        std::vector<OpKey> names, bool scratch) {
   auto G = std::make_unique<Group>();
   G->dq = src.dq;
   G->parity = src.parity;
   G->lay = src.lay;
   G->names = std::move(names);
-  G->alloc(tab);
+  G->alloc(tab, stream, scratch ? &step_arena : nullptr);
   const int nout = (int)coef.size(), nin = src.n();
   if (nout == 0 || nin == 0 || src.lay.size == 0) return G;
   std::vector<double> c((size_t)nout * nin);
   for (int r = 0; r < nout; ++r)
     for (int m = 0; m < nin; ++m) c[(size_t)r * nin + m] = coef[r][m];
-  double* dc = (double*)dev_alloc(c.size() * sizeof(double));
-  dev_h2d(dc, c.data(), c.size() * sizeof(double));
+  // the coefficients are read by the launch below only: staged in the ring
+  double* dc = (double*)ring->put(c.data(), c.size() * sizeof(double));
   int cb = tab.add(dc);
   GemmList gl;
   // out (nout x S) = C (nout x nin) * src (nin x S); split N so a task stays < 2^31 elements
@@ -152,8 +154,6 @@ std::unique_ptr<Group> Builder::combine(const Group& src, const std::vector<std:
     gl.end();
   }
   run(gl);
-  dev_sync(stream);
-  dev_free(dc);
   tab.set(cb, nullptr);
   return G;
 }
@@ -188,7 +188,8 @@ int spin(int p) { return p & 1; }
 
 }  // namespace
 
-std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A, const Basis& newbasis) {
+std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A, const Basis& newbasis,
+                                     bool last) {
   const bool left = X.left;
   const int aj = 2 * j, bj = 2 * j + 1;
   auto Zp = std::make_unique<Block>();
@@ -261,12 +262,19 @@ std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A,
   for (int m : Z.ext_a) Z.g[G_SA].names.push_back({'S', m, -1});
   for (int m : Z.ext_b) Z.g[G_SB].names.push_back({'S', m, -1});
   Z.g[G_H].names.push_back({'H', -1, -1});
+  size_t zbytes = 0;
   for (int gid = 0; gid < NG; ++gid) {
     Z.g[gid].dq = GROUP_DQ[gid];
     Z.g[gid].parity = GROUP_PAR[gid];
     Z.g[gid].lay = make_layout(Z.basis, GROUP_DQ[gid]);
-    Z.g[gid].alloc(tab);
+    zbytes += ((size_t)std::max<int64_t>(1, (int64_t)Z.g[gid].n() * Z.g[gid].lay.size) * sizeof(double) + 255) &
+              ~size_t(255);
   }
+  if (!last) {
+    Z.arena.reset(new DeviceArena());
+    Z.arena->reserve(zbytes);
+  }
+  for (int gid = 0; gid < NG; ++gid) Z.g[gid].alloc(tab, stream, Z.arena.get());
 
   // ---- families
   using namespace site;
@@ -391,7 +399,7 @@ std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A,
   };
   auto make_inter = [&](const Group& src, std::vector<std::vector<double>> rows) -> const Group* {
     std::vector<OpKey> nm(rows.size(), OpKey{'X', -1, -1});
-    inter.push_back(combine(src, rows, nm));
+    inter.push_back(combine(src, rows, nm, true));
     return inter.back().get();
   };
   auto nonzero = [](const std::vector<double>& v) {
@@ -538,8 +546,7 @@ std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A,
       fam(G_H, 0, 1, Q, 0, false, mul(CRE[ps], ANN[ss]), 0);
     }
 
-  // ---- execute families
-  dev_sync(stream);
+  // ---- execute families (stream order covers the intermediates' launches)
   const Basis& XB = X.basis;
   const Basis& ZB = Z.basis;
   // coefficient vectors to the device
@@ -552,8 +559,8 @@ std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A,
     }
   double* dcv = nullptr;
   int cvbuf = -1;
-  if (!cvall.empty()) {
-    dcv = (double*)dev_alloc(cvall.size() * sizeof(double));
+  if (!cvall.empty()) {  // read by launches all through the step: not in the ring
+    dcv = (double*)step_arena.take(cvall.size() * sizeof(double));
     dev_h2d(dcv, cvall.data(), cvall.size() * sizeof(double));
     cvbuf = tab.add(dcv);
   }
@@ -596,10 +603,8 @@ std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A,
       size_t per = (size_t)tstride * sizeof(double);
       chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)f.count, scratch_budget / per));
       size_t need = per * (size_t)chunk;
-      if (need > Tcap) {
-        dev_sync(stream);
-        dev_free(T);
-        T = (double*)dev_alloc(need);
+      if (need > Tcap) {  // every T block is written by phase 1 before phase 2 reads it
+        T = (double*)step_arena.take(need);
         Tcap = need;
         tab.set(Tbuf, T);
       }
@@ -689,14 +694,13 @@ std::unique_ptr<Block> Builder::grow(const Block& X, int j, const SiteTensor& A,
     }
   }
   dev_sync(stream);
-  dev_free(T);
   tab.set(Tbuf, nullptr);
-  dev_free(dcv);
   if (cvbuf >= 0) tab.set(cvbuf, nullptr);
   for (auto& g : inter) {
     tab.set(g->buf, nullptr);
     g->free_dev();
   }
+  step_arena.reset();
   return Zp;
 }
 

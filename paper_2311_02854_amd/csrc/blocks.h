@@ -36,9 +36,11 @@ struct Group {
   int buf = -1;       // id in the owning DevTable
   float* dev32 = nullptr;  // reduced-precision copy (sigma operators only)
   int buf32 = -1;
+  bool in_arena = false;   // dev is carved from a DeviceArena (not freed here)
   int n() const { return (int)names.size(); }
   int64_t stride() const { return lay.size; }
-  void alloc(DevTable& tab);
+  // zero-filled on `stream`; from `arena` if given
+  void alloc(DevTable& tab, void* stream, DeviceArena* arena = nullptr);
   void free_dev();
 };
 
@@ -52,9 +54,11 @@ struct Block {
   Basis basis;             // in-block electron numbers per sector (MPS sector order)
   std::vector<Group> g;    // NG groups
   std::vector<int> ext_a, ext_b;  // external alpha / beta modes, in S member order
+  std::unique_ptr<DeviceArena> arena;  // one allocation holding the groups of a grown block
   ~Block() { free_dev(); }
   void free_dev() {
     for (auto& x : g) x.free_dev();
+    if (arena) arena->release();
   }
   int member(int gid, OpKey k) const;  // -1 if absent
 };
@@ -94,16 +98,26 @@ struct Builder {
   int Na, Nb;
   BuildStats st;
   size_t scratch_budget = size_t(2) << 30;  // bytes of T scratch per renormalization chunk
+  // task lists, pointer tables and one-launch coefficient arrays of the
+  // build's many short launches: staged asynchronously (no host wait)
+  std::unique_ptr<UploadRing> ring;
+  static constexpr size_t RING_BYTES = size_t(256) << 20;
+  // intermediates, T scratch and coefficient arrays of one growth step
+  DeviceArena step_arena;
 
   Builder(const Integrals& ints, DevTable& t, void* s, int na, int nb)
-      : I(ints), tab(t), stream(s), Na(na), Nb(nb) {}
+      : I(ints), tab(t), stream(s), Na(na), Nb(nb), ring(new UploadRing(RING_BYTES, s)) {}
 
   std::unique_ptr<Block> vacuum(bool left);
   // grow a left block by site j (= its nsites) or a right block by site j (= first_site-1)
-  std::unique_ptr<Block> grow(const Block& X, int j, const SiteTensor& A, const Basis& newbasis);
+  // (last: the block is kept for sigma; its groups are separate allocations
+  // so that single groups can be freed, else they share one)
+  std::unique_ptr<Block> grow(const Block& X, int j, const SiteTensor& A, const Basis& newbasis,
+                              bool last = false);
   // intermediate group: out[r] = sum_m coef[r][m] * src member m  (same layout as src)
+  // (scratch: the result lives in step_arena, valid until the step ends)
   std::unique_ptr<Group> combine(const Group& src, const std::vector<std::vector<double>>& coef,
-                                 std::vector<OpKey> names);
+                                 std::vector<OpKey> names, bool scratch = false);
   void run(GemmList& gl);
 };
 

@@ -87,6 +87,11 @@ size_t scratch_bytes();
 void scratch_init(int device);
 void* scratch_get(int device);
 void* dev_alloc(size_t bytes);          // zero-filled; throws Error(ENOMEM)
+void* dev_alloc_nozero(size_t bytes);   // contents undefined; throws Error(ENOMEM)
+void* host_alloc_pinned(size_t bytes);  // page-locked host memory; throws Error(ENOMEM)
+void host_free_pinned(void* p);
+// asynchronous copy on `stream` from page-locked host memory
+void dev_h2d_async(void* dst, const void* pinned_src, size_t bytes, void* stream);
 void dev_free(void* p);
 void dev_h2d(void* dst, const void* src, size_t bytes);            // synchronous
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);  // synchronous
@@ -125,6 +130,7 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
                  int64_t grid_per_xcd, void* stream);
 
 void k_fill(double* x, double v, int64_t n, void* stream);
+void k_zero_bytes(void* p, size_t bytes, void* stream);  // p 8-byte aligned
 void k_fill_f(float* x, float v, int64_t n, void* stream);
 void k_d2f(const double* x, float* y, int64_t n, void* stream);
 void k_f2d(const float* x, double* y, int64_t n, void* stream);

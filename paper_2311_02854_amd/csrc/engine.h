@@ -12,6 +12,115 @@
 
 namespace dmrg {
 
+// Staging for streams of short launches (the operator build): task lists,
+// pointer tables and coefficient arrays are copied asynchronously on the
+// stream from a page-locked host ring into a device ring, so the host never
+// waits for the GPU to upload the next launch.  A copy stays valid until the
+// ring wraps; the ring then synchronises the stream first (no launch still
+// reads it) and bumps its generation, which invalidates cached copies.
+class UploadRing {
+ public:
+  UploadRing(size_t cap, void* stream) : cap_(cap), stream_(stream) {
+    dev_ = (char*)dev_alloc_nozero(cap_);
+    try {
+      host_ = (char*)host_alloc_pinned(cap_);
+    } catch (...) {
+      dev_free(dev_);
+      throw;
+    }
+  }
+  ~UploadRing() {
+    dev_sync(stream_);
+    dev_free(dev_);
+    host_free_pinned(host_);
+  }
+  UploadRing(const UploadRing&) = delete;
+  UploadRing& operator=(const UploadRing&) = delete;
+  // Stage a copy (issued by the next flush(); put() = stage + flush).
+  void* stage(const void* src, size_t bytes) {
+    const size_t b = ((bytes ? bytes : 1) + 255) & ~size_t(255);
+    DMRG_CHECK(b <= cap_, DMRG_ENOMEM, "upload of " + std::to_string(bytes) + " bytes exceeds the staging ring");
+    if (head_ + b > cap_) {
+      flush();
+      dev_sync(stream_);
+      head_ = pending_ = 0;
+      ++gen_;
+    }
+    if (bytes) std::memcpy(host_ + head_, src, bytes);
+    void* p = dev_ + head_;
+    head_ += b;
+    return p;
+  }
+  void flush() {
+    if (head_ > pending_) dev_h2d_async(dev_ + pending_, host_ + pending_, head_ - pending_, stream_);
+    pending_ = head_;
+  }
+  void* put(const void* src, size_t bytes) {
+    void* p = stage(src, bytes);
+    flush();
+    return p;
+  }
+  uint64_t generation() const { return gen_; }
+
+ private:
+  char* dev_ = nullptr;
+  char* host_ = nullptr;
+  size_t cap_, head_ = 0, pending_ = 0;  // [pending_, head_) staged, not yet copied
+  uint64_t gen_ = 0;
+  void* stream_;
+};
+
+// Device memory for short-lived buffers of one step (the operator build's
+// intermediates and scratch): carved from large chunks, released all at
+// once by reset(), which keeps one chunk as large as all the step used so
+// that the next step needs no allocation (a hipMalloc or hipFree of a large
+// buffer costs about a millisecond).  reset() and release() may only be
+// called once no launch still uses the memory.
+class DeviceArena {
+ public:
+  DeviceArena() = default;
+  ~DeviceArena() { release(); }
+  DeviceArena(const DeviceArena&) = delete;
+  DeviceArena& operator=(const DeviceArena&) = delete;
+  void* take(size_t bytes) {
+    const size_t b = ((bytes ? bytes : 1) + 255) & ~size_t(255);
+    if (chunks_.empty() || head_ + b > chunks_.back().second) {
+      const size_t last = chunks_.empty() ? 0 : chunks_.back().second;
+      const size_t cap = std::max(b, std::max(2 * last, size_t(64) << 20));
+      chunks_.push_back({(char*)dev_alloc_nozero(cap), cap});
+      head_ = 0;
+    }
+    void* p = chunks_.back().first + head_;
+    head_ += b;
+    return p;
+  }
+  // one chunk of exactly `bytes` (256-aligned pieces must fit), before any take
+  void reserve(size_t bytes) {
+    DMRG_CHECK(chunks_.empty(), DMRG_EINTERNAL, "reserve on a used arena");
+    const size_t cap = (bytes + 255) & ~size_t(255);
+    chunks_.push_back({(char*)dev_alloc_nozero(cap ? cap : 256), cap ? cap : 256});
+    head_ = 0;
+  }
+  void reset() {
+    if (chunks_.size() > 1) {
+      size_t total = 0;
+      for (auto& c : chunks_) total += c.second;
+      release();
+      chunks_.push_back({(char*)dev_alloc_nozero(total), total});
+    }
+    head_ = 0;
+  }
+  void release() {
+    for (auto& c : chunks_) dev_free(c.first);
+    chunks_.clear();
+    head_ = 0;
+  }
+
+ private:
+  std::vector<std::pair<char*, size_t>> chunks_;
+  size_t head_ = 0;
+};
+
 // Table of device pointers addressed by buffer id (ids 0 and 1 are the
 // per-launch pointers p0 / p1 of gemm_launch).
 class DevTable {
@@ -20,14 +129,23 @@ class DevTable {
   ~DevTable() { dev_free(dev_); }
   DevTable(const DevTable&) = delete;
   DevTable& operator=(const DevTable&) = delete;
+  // ids released by set(id, nullptr) are handed out again (ids 0 and 1 are
+  // the per-launch pointers)
   int add(void* p) {
+    dirty_ = dirty_ring_ = true;
+    if (!free_.empty()) {
+      const int id = free_.back();
+      free_.pop_back();
+      ptrs_[id] = p;
+      return id;
+    }
     ptrs_.push_back(p);
-    dirty_ = true;
     return (int)ptrs_.size() - 1;
   }
   void set(int id, void* p) {
+    if (!p && ptrs_[id] && id >= 2) free_.push_back(id);
     ptrs_[id] = p;
-    dirty_ = true;
+    dirty_ = dirty_ring_ = true;
   }
   void* get(int id) const { return ptrs_[id]; }
   int size() const { return (int)ptrs_.size(); }
@@ -43,9 +161,23 @@ class DevTable {
     }
     return dev_;
   }
+  // a copy of the table in the staging ring (kept while the table and the
+  // ring's generation are unchanged)
+  void* const* device(UploadRing& ring) {
+    if (dirty_ring_ || !ring_copy_ || ring_gen_ != ring.generation()) {
+      ring_copy_ = (void**)ring.put(ptrs_.data(), ptrs_.size() * sizeof(void*));
+      ring_gen_ = ring.generation();
+      dirty_ring_ = false;
+    }
+    return ring_copy_;
+  }
 
  private:
   std::vector<void*> ptrs_;
+  std::vector<int> free_;
+  void** ring_copy_ = nullptr;
+  uint64_t ring_gen_ = 0;
+  bool dirty_ring_ = true;
   void** dev_ = nullptr;
   size_t cap_ = 0;
   bool dirty_ = true;
@@ -240,28 +372,32 @@ class GemmList {
   // to XCDs (longest processing time first) and upload the per-XCD lists:
   // into fresh device allocations, or into `arena` (nothing is allocated;
   // the lists then live as long as the arena's memory is left alone).
-  void upload(int tl, Arena* arena = nullptr) {
+  void upload(int tl, Arena* arena = nullptr, UploadRing* ring = nullptr) {
     DMRG_CHECK(tl >= 0 && tl < NTILE, DMRG_EINVAL, "unknown tile shape");
     free_dev(dev_[tl]);
     if (tasks.empty()) return;
     Dev& D = dev_[tl];
-    D.external = arena != nullptr;
-    auto alloc = [&](size_t b) -> void* { return arena ? arena->take(b) : dev_alloc(b); };
+    D.external = arena != nullptr || ring != nullptr;
+    // device copy of a host array: a fresh allocation, the arena, or the ring
+    auto put = [&](const void* src, size_t b) -> void* {
+      if (ring) return ring->stage(src, b);  // one copy for the whole list (flushed below)
+      void* p = arena ? arena->take(b) : dev_alloc_nozero(b);
+      dev_h2d(p, src, b);
+      return p;
+    };
     std::vector<GTask> src;
     std::vector<GContrib> cx;
     const GContrib* cs = contribs.data();
     if (tl == TILE_EDGE) {
       split_edges(src, cx);
       cs = cx.data();
-      D.contribs = (GContrib*)alloc((cx.size() + 1) * sizeof(GContrib));
-      if (!cx.empty()) dev_h2d(D.contribs, cx.data(), cx.size() * sizeof(GContrib));
+      D.contribs = (GContrib*)put(cx.data(), cx.size() * sizeof(GContrib));
       D.ncontribs = cx.size();
     } else {
       src = tasks;
       for (GTask& g : src) g.shape = tl;
-      if (arena) {  // own copy of the contributions, in the arena
-        D.contribs = (GContrib*)alloc((contribs.size() + 1) * sizeof(GContrib));
-        if (!contribs.empty()) dev_h2d(D.contribs, contribs.data(), contribs.size() * sizeof(GContrib));
+      if (D.external) {  // own copy of the contributions, in the arena or ring
+        D.contribs = (GContrib*)put(contribs.data(), contribs.size() * sizeof(GContrib));
         D.ncontribs = contribs.size();
       } else if (!dcontribs_) {
         dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
@@ -344,9 +480,9 @@ class GemmList {
       units.push_back(jb);
       D.map.nunits[x] = (int64_t)units.size() - 1 - D.map.unit_begin[x];
     }
-    D.units = (int64_t*)alloc(units.size() * sizeof(int64_t));
-    dev_h2d(D.units, units.data(), units.size() * sizeof(int64_t));
-    D.counters = (unsigned*)alloc(64 * NXCD * sizeof(unsigned));
+    D.units = (int64_t*)put(units.data(), units.size() * sizeof(int64_t));
+    const std::vector<unsigned> zeros(64 * NXCD, 0u);
+    D.counters = (unsigned*)put(zeros.data(), zeros.size() * sizeof(unsigned));
     D.map.units = D.units;
     D.map.counters = D.counters;
     D.map.task_begin[NXCD] = (int)dev.size();
@@ -365,10 +501,9 @@ class GemmList {
       }
     }
     D.map.bucket_begin[NXCD] = (int)bucket.size();
-    D.bucket = (int*)alloc(std::max<size_t>(1, bucket.size()) * sizeof(int));
-    dev_h2d(D.bucket, bucket.data(), bucket.size() * sizeof(int));
-    D.tasks = (GTask*)alloc(dev.size() * sizeof(GTask));
-    dev_h2d(D.tasks, dev.data(), dev.size() * sizeof(GTask));
+    D.bucket = (int*)put(bucket.data(), bucket.size() * sizeof(int));
+    D.tasks = (GTask*)put(dev.data(), dev.size() * sizeof(GTask));
+    if (ring) ring->flush();
     D.ntasks = (int)dev.size();
   }
   void upload() { upload(tile); }

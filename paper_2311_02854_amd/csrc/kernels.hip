@@ -75,8 +75,37 @@ void* dev_alloc(size_t bytes) {
   return p;
 }
 
+void* dev_alloc_nozero(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(DMRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
 void dev_free(void* p) {
   if (p) (void)hipFree(p);
+}
+
+void* host_alloc_pinned(size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipHostMalloc(&p, bytes ? bytes : 256, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(DMRG_ENOMEM, "hipHostMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+void host_free_pinned(void* p) {
+  if (p) (void)hipHostFree(p);
+}
+
+void dev_h2d_async(void* dst, const void* src, size_t bytes, void* stream) {
+  if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, S(stream)));
 }
 
 void dev_h2d(void* dst, const void* src, size_t bytes) {
@@ -893,6 +922,13 @@ __global__ void scale_kernel(double* y, double s, int64_t n) {
 void k_fill(double* x, double v, int64_t n, void* s) {
   if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, v, n);
   dev_check("k_fill");
+}
+void k_zero_bytes(void* p, size_t bytes, void* s) {
+  DMRG_CHECK(((uintptr_t)p & 7) == 0 && bytes % 8 == 0, DMRG_EINTERNAL,
+             "k_zero_bytes needs 8-byte aligned whole words");
+  const int64_t n = (int64_t)(bytes / 8);
+  if (n > 0) hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), (double*)p, 0.0, n);
+  dev_check("k_zero_bytes");
 }
 void k_fill_f(float* x, float v, int64_t n, void* s) {
   if (n > 0) hipLaunchKernelGGL(fill_f_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), x, v, n);

@@ -227,7 +227,7 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
     int64_t bc = first_blk[j];
     auto A = upload_site(j, labels, dims, blk_off, bc, data);
     A->buf = tab.add(A->dev);
-    auto Z = bld.grow(*Lblk, j, *A, make_basis(labels[j + 1], dims[j + 1], true, Na, Nb));
+    auto Z = bld.grow(*Lblk, j, *A, make_basis(labels[j + 1], dims[j + 1], true, Na, Nb), j == bond - 1);
     dev_sync(stream);
     tab.set(A->buf, nullptr);
     Lblk = std::move(Z);
@@ -238,7 +238,7 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
     int64_t bc = first_blk[j];
     auto A = upload_site(j, labels, dims, blk_off, bc, data);
     A->buf = tab.add(A->dev);
-    auto Z = bld.grow(*Rblk, j, *A, make_basis(labels[j], dims[j], false, Na, Nb));
+    auto Z = bld.grow(*Rblk, j, *A, make_basis(labels[j], dims[j], false, Na, Nb), j == bond + 2);
     dev_sync(stream);
     tab.set(A->buf, nullptr);
     Rblk = std::move(Z);

@@ -125,6 +125,11 @@ void* dev_alloc(size_t bytes) {
   return (void*)a;
 }
 
+void* dev_alloc_nozero(size_t bytes) { return dev_alloc(bytes); }
+void* host_alloc_pinned(size_t bytes) { return new char[bytes ? bytes : 1]; }
+void host_free_pinned(void* p) { delete[] (char*)p; }
+void dev_h2d_async(void* dst, const void* src, size_t bytes, void*) { dev_h2d(dst, src, bytes); }
+
 void dev_free(void* p) {
   if (!p) return;
   auto it = g_alloc.find((uint64_t)p);
@@ -341,6 +346,7 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
 // ---- vector kernels: range checks only ---------------------------------------
 
 void k_fill(double* x, double, int64_t n, void*) { check(x, 0, n * 8, "k_fill"); }
+void k_zero_bytes(void* p, size_t bytes, void*) { check(p, 0, (int64_t)bytes, "k_zero_bytes"); }
 void k_fill_f(float* x, float, int64_t n, void*) { check(x, 0, n * 4, "k_fill_f"); }
 void k_d2f(const double* x, float* y, int64_t n, void*) {
   check(x, 0, n * 8, "k_d2f in");
