@@ -258,6 +258,43 @@ int dmrg_davidson(dmrg_ctx* ctx, dmrg_ops* ops, double* psi,
                   dmrg_davidson_stats* stats);
 void dmrg_davidson_default_opts(dmrg_davidson_opts* opts);
 
+/* ---- Decimation: the truncation step of the two-dot sweep (Sec. 2.1) ----
+ *
+ * dmrg_decimate splits the two-dot vector psi (device, n_psi, the layout of
+ * ops) at the bond between the dots, bond+1.  For every sector q of that
+ * bond (electron numbers of sites 0..bond) it forms the reduced density
+ * matrix of one side and diagonalises it on the GPU:
+ *   direction 0 (sweeping left to right): rows (l, n1), the left block state
+ *     and the first dot, with q(l) + q(n1) = q;
+ *   direction 1 (right to left): rows (n2, r) with q(r) - q(n2) = q.
+ * The eigenvalues are the squared Schmidt coefficients.  The D largest over
+ * all sectors are kept (ties: lower sector first); with cutoff > 0 only those
+ * whose weight exceeds cutoff * <psi|psi>, with cutoff = 0 zero weights too
+ * (so that D >= the full dimension keeps the enlarged block's whole space); their eigenvectors form the new site tensor, in the
+ * dmrg_mps format:
+ *   direction 0: A[bond], left-canonical, blocks (il at bond, n, iq at bond+1);
+ *   direction 1: A[bond+1], right-canonical, blocks (iq at bond+1, n, ir at bond+2);
+ * with iq indexing the kept sectors of bond+1 in increasing (q_alpha, q_beta).
+ * A block whose rows do not occur in psi is zero.  out receives the sizes,
+ * the number of states kept, the discarded weight (weight of the dropped
+ * states over <psi|psi>) and the von Neumann entropy of the kept weights.
+ * The result stays in ops until the next call; dmrg_decimation_get copies it
+ * to caller arrays of out->nsec (sec_qn: 2 ints each, sec_dim), out->nblk
+ * (blk_off, offsets into data) and out->ndata (data) entries; any may be
+ * NULL.  Synchronous.  DMRG_EINVAL: D < 1, unknown direction, cutoff outside
+ * [0, 1), zero psi, or no state kept. */
+typedef struct {
+  int nsec;
+  int kept;
+  int64_t nblk;
+  int64_t ndata;
+  double discarded;
+  double entropy;
+} dmrg_decimation_info;
+int dmrg_decimate(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi, int D, int direction, double cutoff,
+                  dmrg_decimation_info* out);
+int dmrg_decimation_get(const dmrg_ops* ops, int* sec_qn, int* sec_dim, int64_t* blk_off, double* data);
+
 /* ---- Learned Davidson preconditioner (an addition to the paper's method) ----
  *
  * A Davidson correction is t_i = g_i * d_i: d_i = r_i / (theta - H_ii) is the

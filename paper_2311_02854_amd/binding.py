@@ -20,6 +20,7 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ESHAPE", -3: "DMRG_ENOMEM",
 
 EXPORTS = ["dmrg_create", "dmrg_destroy", "dmrg_last_error", "dmrg_build_ops", "dmrg_ops_destroy",
            "dmrg_ops_layout", "dmrg_ops_stats", "dmrg_sigma", "dmrg_diag", "dmrg_diag_noalloc", "dmrg_sigma_batched",
+           "dmrg_decimate", "dmrg_decimation_get",
            "dmrg_davidson", "dmrg_davidson_default_opts", "dmrg_profile", "dmrg_mlp_nweights",
            "dmrg_mlp_init", "dmrg_mlp_collect", "dmrg_mlp_train", "dmrg_mlp_apply", "dmrg_autotune",
            "dmrg_launch_shape"]
@@ -59,6 +60,11 @@ class DavidsonOpts(C.Structure):
                 ("trace", C.POINTER(C.c_double)), ("trace_cap", C.c_int), ("precond_shift", C.c_double)]
 
 
+class DecimationInfo(C.Structure):
+    _fields_ = [("nsec", C.c_int), ("kept", C.c_int), ("nblk", C.c_int64), ("ndata", C.c_int64),
+                ("discarded", C.c_double), ("entropy", C.c_double)]
+
+
 class DavidsonStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("sigma_fp64", C.c_int), ("residual", C.c_double),
                 ("seconds", C.c_double), ("seconds_to_ref", C.c_double), ("iters_to_ref", C.c_int),
@@ -88,6 +94,8 @@ def load(path=None):
     lib.dmrg_sigma.argtypes = [vp, vp, vp, vp, C.c_int]
     lib.dmrg_diag.argtypes = [vp, vp, vp]
     lib.dmrg_diag_noalloc.argtypes = [vp, vp, vp]
+    lib.dmrg_decimate.argtypes = [vp, vp, vp, C.c_int, C.c_int, C.c_double, C.POINTER(DecimationInfo)]
+    lib.dmrg_decimation_get.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), i64p, C.POINTER(C.c_double)]
     lib.dmrg_sigma_batched.argtypes = [vp, C.c_int, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_int, C.c_int]
     lib.dmrg_autotune.argtypes = [vp, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.dmrg_launch_shape.argtypes = [vp, C.c_int, C.c_int, C.c_int64]
@@ -203,6 +211,22 @@ class Ops:
 
     def diag(self, out_ptr):
         self.ctx._check(self.ctx.lib.dmrg_diag(self.ctx.h, self.h, C.c_void_p(out_ptr)))
+
+    def decimate(self, psi_ptr, D, direction=0, cutoff=0.0):
+        """Keep the D most important states of psi at the bond between the dots.
+        Returns dict(sec_qn[nsec, 2], sec_dim[nsec], blk_off[nblk], data[ndata], kept, discarded, entropy)."""
+        info = DecimationInfo()
+        self.ctx._check(self.ctx.lib.dmrg_decimate(self.ctx.h, self.h, C.c_void_p(psi_ptr), int(D), int(direction),
+                                                   float(cutoff), C.byref(info)))
+        qn = np.zeros((max(1, info.nsec), 2), np.int32)
+        dim = np.zeros(max(1, info.nsec), np.int32)
+        off = np.zeros(max(1, info.nblk), np.int64)
+        data = np.zeros(max(1, info.ndata), np.float64)
+        self.ctx._check(self.ctx.lib.dmrg_decimation_get(self.h, _p(qn, C.c_int), _p(dim, C.c_int),
+                                                         _p(off, C.c_int64), _p(data, C.c_double)))
+        return {"sec_qn": qn[:info.nsec], "sec_dim": dim[:info.nsec], "blk_off": off[:info.nblk],
+                "data": data[:info.ndata], "kept": info.kept, "discarded": info.discarded,
+                "entropy": info.entropy}
 
     def diag_noalloc(self, out_ptr):
         """diag(H) with the library's static scratch instead of allocations."""

@@ -22,7 +22,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
 
 HIP_SOURCES = ["kernels.hip", "mlp.hip"]
-CXX_SOURCES = ["blocks.cpp", "ops.cpp", "davidson.cpp", "mlp.cpp", "batch.cpp", "capi.cpp"]
+CXX_SOURCES = ["blocks.cpp", "ops.cpp", "davidson.cpp", "decimate.cpp", "mlp.cpp", "batch.cpp", "capi.cpp"]
 
 
 def _run(cmd):
@@ -44,7 +44,8 @@ def build(verbose=False):
         list(ex.map(_run, jobs))
     objs = [os.path.join(OBJ, s + ".o") for s in HIP_SOURCES + CXX_SOURCES]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
+          "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

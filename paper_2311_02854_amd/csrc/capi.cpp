@@ -1,5 +1,6 @@
 // extern "C" entry points of include/dmrg.h.  Every call catches exceptions
 // and turns them into status codes plus a per-context message.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -284,6 +285,41 @@ int dmrg_davidson(dmrg_ctx* ctx, dmrg_ops* ops, double* psi, const dmrg_davidson
     ops->p->end_call(ctx->stream);
     return rc;
   });
+}
+
+int dmrg_decimate(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi, int D, int direction, double cutoff,
+                  dmrg_decimation_info* out) {
+  if (!ctx || !ops || !psi || !out) return DMRG_EINVAL;
+  return guarded(ctx, [&] {
+    dmrg::Ops& O = *ops->p;
+    O.begin_call(ctx->stream);
+    dmrg::decimate_run(O, psi, D, direction, cutoff, ctx->stream);
+    O.end_call(ctx->stream);
+    const dmrg::Decimation& R = *O.decim;
+    out->nsec = (int)R.sec.size();
+    out->nblk = (int64_t)R.blk_off.size();
+    out->ndata = (int64_t)R.data.size();
+    out->kept = 0;
+    for (int d : R.dim) out->kept += d;
+    out->discarded = R.discarded;
+    out->entropy = R.entropy;
+    return (int)DMRG_OK;
+  });
+}
+
+int dmrg_decimation_get(const dmrg_ops* ops, int* sec_qn, int* sec_dim, int64_t* blk_off, double* data) {
+  if (!ops || !ops->p->decim) return DMRG_EINVAL;
+  const dmrg::Decimation& R = *ops->p->decim;
+  for (size_t i = 0; i < R.sec.size(); ++i) {
+    if (sec_qn) {
+      sec_qn[2 * i] = R.sec[i].a;
+      sec_qn[2 * i + 1] = R.sec[i].b;
+    }
+    if (sec_dim) sec_dim[i] = R.dim[i];
+  }
+  if (blk_off) std::copy(R.blk_off.begin(), R.blk_off.end(), blk_off);
+  if (data) std::copy(R.data.begin(), R.data.end(), data);
+  return DMRG_OK;
 }
 
 int dmrg_mlp_nweights(void) { return dmrg::mlp_nweights(); }

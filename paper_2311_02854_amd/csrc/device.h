@@ -146,6 +146,13 @@ void k_multidot(const double* V, int64_t ld, int m, const double* x, int64_t n, 
 void k_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* stream);
 // y[k] -= sum_j c[j] V[j*ld + k]
 void k_sub_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* stream);
+// Symmetric eigen-decomposition of an n x n matrix in device memory (rocSOLVER
+// syevd): A (lda >= n, either storage order: A is symmetric) is overwritten by
+// the eigenvectors, stored column-major (column j at A + j*lda), and w[n]
+// receives the eigenvalues in ascending order.  Stream-ordered; throws
+// Error(EINTERNAL) if the solver did not converge (checked at the next dev_sync
+// through *info, an int in device memory).
+void dev_syevd(double* A, int n, int lda, double* w, double* work_e, int* info, void* stream);
 // Symmetric eigen-decomposition of a small m x m matrix (m <= 32) by cyclic
 // Jacobi; writes eigenvalues ascending to w[m] and eigenvectors (columns) to Z.
 void k_small_eigh(const double* G, int ld, int m, double* w, double* Z, void* stream);

@@ -9,7 +9,12 @@
 // is fixed, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <atomic>
+#include <map>
+#include <mutex>
 
 #include <chrono>
 #include <cstdio>
@@ -1014,6 +1019,30 @@ void k_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, d
 void k_sub_lincomb(const double* V, int64_t ld, int m, const double* c, int64_t n, double* y, void* s) {
   hipLaunchKernelGGL(lincomb_kernel, dim3(nblocks(n)), dim3(256), 0, S(s), V, ld, m, c, n, y, 1);
   dev_check("k_sub_lincomb");
+}
+
+// rocSOLVER handles, one per (device, stream), kept for the process lifetime.
+static rocblas_handle solver_handle(void* stream) {
+  static std::mutex mu;
+  static std::map<std::pair<int, void*>, rocblas_handle> handles;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = handles.find({dev, stream});
+  if (it != handles.end()) return it->second;
+  rocblas_handle h = nullptr;
+  DMRG_CHECK(rocblas_create_handle(&h) == rocblas_status_success, DMRG_EHIP, "rocblas_create_handle failed");
+  DMRG_CHECK(rocblas_set_stream(h, S(stream)) == rocblas_status_success, DMRG_EHIP, "rocblas_set_stream failed");
+  handles[{dev, stream}] = h;
+  return h;
+}
+
+void dev_syevd(double* A, int n, int lda, double* w, double* work_e, int* info, void* stream) {
+  if (n <= 0) return;
+  const rocblas_status st = rocsolver_dsyevd(solver_handle(stream), rocblas_evect_original, rocblas_fill_upper, n,
+                                             A, lda, w, work_e, info);
+  DMRG_CHECK(st == rocblas_status_success, DMRG_EHIP, "rocsolver_dsyevd failed to launch");
+  dev_check("dev_syevd");
 }
 
 // Cyclic Jacobi on one wave; matrix in LDS.  m <= 32.

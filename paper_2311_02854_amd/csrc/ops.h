@@ -31,6 +31,18 @@ struct SFam {
   const char* tag = "";
 };
 
+// Result of the last decimation of a two-dot vector (decimate.cpp): the kept
+// sectors of the bond between the dots (sorted by electron numbers) and the
+// new site tensor in the dmrg_mps block order.
+struct Decimation {
+  int direction = 0;
+  std::vector<QN> sec;
+  std::vector<int> dim;
+  std::vector<int64_t> blk_off;
+  std::vector<double> data;
+  double discarded = 0, entropy = 0;
+};
+
 struct Ops {
   int K = 0, Na = 0, Nb = 0, bond = 0, device = 0;
   double ecore = 0;
@@ -82,6 +94,7 @@ struct Ops {
   // ordering across streams: the handle's scratch (R-step slots, FP32
   // copies, unit counters) is reused by every call, so a call on a stream
   // other than the last one waits for the last call's work first
+  std::unique_ptr<Decimation> decim;  // last dmrg_decimate result
   void* order_ev = nullptr;
   void* last_stream = nullptr;
   bool used = false;
@@ -131,6 +144,11 @@ using DavidsonHook = std::function<void(const double* x, const double* r, const 
                                         const double* theta_dev, const double* V, int m, int iter)>;
 int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* energy, dmrg_davidson_stats* st,
                  void* stream, const DavidsonHook& hook = DavidsonHook());
+
+// keep the D most important states of psi at the bond between the dots
+// (direction 0: left side, new A[k]; 1: right side, new A[k+1]); result in
+// O.decim.  Synchronous.
+void decimate_run(Ops& O, const double* psi, int D, int direction, double cutoff, void* stream);
 
 // learned preconditioner (mlp.cpp)
 int mlp_nweights();

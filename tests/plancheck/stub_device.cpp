@@ -404,6 +404,13 @@ void k_gather_diag(const double* src, const int64_t* meta, int nblk, int64_t sst
   }
 }
 void k_scale(double* y, double, int64_t n, void*) { check(y, 0, n * 8, "k_scale"); }
+void dev_syevd(double* A, int n, int lda, double* w, double* work_e, int* info, void*) {
+  if (n <= 0) return;
+  check(A, 0, ((int64_t)(n - 1) * lda + n) * 8, "dev_syevd A");
+  check(w, 0, (int64_t)n * 8, "dev_syevd w");
+  check(work_e, 0, (int64_t)n * 8, "dev_syevd work");
+  check(info, 0, 4, "dev_syevd info");
+}
 
 // The learned preconditioner's kernels are not on the plan paths the checker
 // drives; they only have their vector arguments checked.

@@ -24,7 +24,7 @@ CSRC = os.path.join(ROOT, "paper_2311_02854_amd", "csrc")
 HERE = os.path.join(ROOT, "tests", "plancheck")
 BUILD = os.path.join(HERE, "_build")
 EXE = os.path.join(BUILD, "plancheck")
-PLANNER = ["blocks.cpp", "ops.cpp", "davidson.cpp", "mlp.cpp", "batch.cpp", "capi.cpp"]
+PLANNER = ["blocks.cpp", "ops.cpp", "davidson.cpp", "decimate.cpp", "mlp.cpp", "batch.cpp", "capi.cpp"]
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
 
 
