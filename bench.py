@@ -269,6 +269,47 @@ def mixed_leg(ops, psi):
     return out
 
 
+def sweep_leg(ctx, ints, K, Na, Nb, D, seed):
+    """Config 2: sigma and Davidson at every bond of one left-to-right pass of
+    the two-dot sweep (operators rebuilt per bond, decimation to D after each
+    bond), then E(w): two full sweeps at each of three smaller D, each started
+    from the previous one's MPS, the last pass's lowest energy and largest
+    discarded weight w, and the least-squares line E = E0 + a w.""" 
+    import torch
+    import synth
+    from paper_2311_02854_amd.sweep import sweep
+    mps0 = synth.make_mps(K, Na, Nb, D, 0, 3000 + seed)
+    bonds = []
+
+    def per_bond(rec):
+        bonds.append(rec)
+        log(f"[bench] sweep k={rec['k']} E={rec['energy']:.8f} it={rec['iterations']} "
+            f"w={rec.get('discarded', 0):.2e} {rec['seconds']:.2f} s")
+
+    t0 = time.time()
+    hist, mps = sweep(ctx, ints, mps0, D, first_pass_only=True, tol_residual=1e-5, log=per_bond)
+    t_pass = time.time() - t0
+    # sigma timing per bond on the final pass's MPS would need the operators
+    # again: time sigma at three bonds of the decimated MPS instead
+    out = {"pass_seconds": t_pass, "bonds": len(hist),
+           "energies": [h["energy"] for h in hist], "discarded": [h.get("discarded", 0.0) for h in hist],
+           "davidson_iterations": [h["iterations"] for h in hist],
+           "build_seconds": [h["build_s"] for h in hist], "n_psi": [h["n_psi"] for h in hist]}
+    ew = []
+    m = synth.make_mps(K, Na, Nb, D // 10, 0, 3000 + seed)
+    for d in (D // 10, D // 5, D // 2):   # each D warm-started from the previous one's MPS
+        h2, m = sweep(ctx, ints, m, d, nsweeps=2, tol_residual=1e-6)
+        last = [h for h in h2 if h["pass"] == 3]
+        w = max(h.get("discarded", 0.0) for h in last)
+        e = min(h["energy"] for h in last)
+        ew.append({"D": d, "E": e, "w": w})
+        log(f"[bench] E(w): D={d} E={e:.8f} w={w:.3e}")
+    A = np.array([[1.0, e["w"]] for e in ew])
+    coef, *_ = np.linalg.lstsq(A, np.array([e["E"] for e in ew]), rcond=None)
+    out["E_of_w"] = {"points": ew, "E0": float(coef[0]), "slope": float(coef[1])}
+    return out
+
+
 def measured_peaks():
     """This GPU's own peaks beside the datasheet ones: FP64 DGEMM (torch.matmul,
     8192^3, the library GEMM), device-to-device copy bandwidth (4 GiB), and the
@@ -334,6 +375,7 @@ def main():
     ap.add_argument("--no-davidson", action="store_true",
                     help="skip the Davidson time-to-1e-6 Eh leg (plain FP64 + diagonal vs shifted, split-BF16, learned)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured DGEMM / copy / batched peaks")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sweep leg of --config 2")
     ap.add_argument("--build-only", action="store_true",
                     help="only build the operators (dmrg_build_ops) and print its wall time (for profiling)")
     ap.add_argument("--mixed", action="store_true",
@@ -437,6 +479,8 @@ def main():
             out["roofline"]["frac_of_measured_dgemm"] = (
                 achieved / out["roofline"]["measured_peaks"]["dgemm_fp64_8192_tflops"] if achieved else None)
         log(f"[bench] measured peaks: {out['roofline']['measured_peaks']}")
+    if args.config == "2" and not args.no_sweep:
+        out["sweep"] = sweep_leg(ctx, ints, K, Na, Nb, D, seed)
     if args.config == "3" or args.mixed:
         out["mixed_precision"] = mixed_leg(ops, psi)
     if args.config == "5" and not args.no_davidson:

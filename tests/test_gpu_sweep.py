@@ -95,3 +95,28 @@ def test_truncated_sweep_follows_oracle(ctx):
         assert (h["pass"], h["k"]) == (r["pass"], r["k"])
         assert abs(h["energy"] - r["energy"]) <= 1e-8
         assert abs(h.get("discarded", 0.0) - r.get("discarded", 0.0)) <= 1e-8
+
+
+def test_energy_extrapolation_in_discarded_weight(ctx):
+    # K=12, 4+4 electrons: D = 400 covers every sector of every bond, so its
+    # converged sweep energy is exact.  Sweeps at D = 12, 18, 24 (each
+    # started from the previous one's MPS) give E(D) above it, decreasing
+    # with the discarded weight w, and the line E = E0 + a w through them
+    # extrapolates closer to the exact energy than the best of them.
+    from paper_2311_02854_amd.sweep import sweep
+    ints = synth.make_integrals(12, 1201)
+    m = synth.make_mps(12, 4, 4, 12, 0, 1202)
+    pts = []
+    for d in (12, 18, 24):
+        hist, m = sweep(ctx, ints, m, d, nsweeps=2, tol_residual=1e-8)
+        last = [h for h in hist if h["pass"] == 3]
+        pts.append((max(h.get("discarded", 0.0) for h in last), min(h["energy"] for h in last)))
+    hist, _ = sweep(ctx, ints, m, 400, nsweeps=2, tol_residual=1e-8, cutoff=0.0)
+    exact = min(h["energy"] for h in hist if h["pass"] == 3)
+    w = np.array([p[0] for p in pts])
+    e = np.array([p[1] for p in pts])
+    a, e0 = np.polyfit(w, e, 1)
+    print(f"E(w) points {pts}; E0={e0:.8f} exact={exact:.8f} best={e.min():.8f}")
+    assert np.all(e >= exact - 1e-8)
+    assert e[0] > e[1] > e[2] and w[0] > w[1] > w[2] > 0
+    assert abs(e0 - exact) < abs(e.min() - exact)
