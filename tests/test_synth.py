@@ -12,7 +12,7 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 def test_dmax_fit_matches_paper_table():
     # Eq. (dmax) of Sec. 3 against the d_max column the paper tabulates
-    rows = np.loadtxt(os.path.join(GOLD, "dmax_table2.txt"))
+    rows = np.loadtxt(os.path.join(GOLD, "dmax_speedup_table.txt"))
     for D, dmax in rows:
         assert abs(dmax_fit(D) - dmax) <= 0.08 * dmax
 
