@@ -114,19 +114,21 @@ def log(*a):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2311_02854_amd", "csrc", "kernels.hip")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm_kernel_f64_sigma_K73_D2000_pmc.md")
+TRAFFIC_PROFILE = {prec: os.path.join(ROOT, "profiles", f"gemm_kernel_{tag}_sigma_K73_D2000_pmc.md")
+                   for prec, tag in (("fp64", "f64"), ("fp32", "f32"), ("bf16x3", "bf16x3"))}
 
 
 def measured_traffic(config, precision):
-    """HBM bytes per sigma call from the committed rocprofv3 PMC summary
-    (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor, KiB -> bytes), or
-    None if there is none for this workload or the GEMM kernel source changed
-    since the counters were taken."""
+    """HBM bytes per sigma call from the committed rocprofv3 PMC summary of
+    this precision (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor,
+    KiB -> bytes), or None if there is none for this workload or the GEMM
+    kernel source changed since the counters were taken."""
     import hashlib
-    if config != "5" or precision != "fp64" or not os.path.exists(TRAFFIC_PROFILE):
+    path = TRAFFIC_PROFILE.get(precision)
+    if config != "5" or path is None or not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(path):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
@@ -367,7 +369,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle cpu_baseline leg")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--tile", type=int, default=None,
-                    help="launch every sigma GEMM with this mode (0-3 uniform tiles, 4 mixed 64/32 strips) "
+                    help="launch every sigma GEMM with this mode (0-3 uniform tiles, 4 mixed 64/32 strips, 5 128x128 "
+                         "on 1024-thread workgroups, 6 128x128 interiors of long-k tasks + the rest mixed) "
                          "instead of autotuning")
     ap.add_argument("--grid", type=int, default=0, help="grid mode with --tile (0 one workgroup per job, -1 dynamic)")
     ap.add_argument("--x-budget-gb", type=float, default=0.0,

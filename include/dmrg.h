@@ -158,11 +158,17 @@ int dmrg_create(dmrg_ctx** ctx, int device, void* hip_stream);
 void dmrg_destroy(dmrg_ctx* ctx);
 const char* dmrg_last_error(const dmrg_ctx* ctx);
 
-/* Scratch budgets of dmrg_build_ops (0 selects the default). */
+/* Scratch budgets and split-k threshold of dmrg_build_ops (0 selects the default). */
 typedef struct {
   size_t x_budget_bytes;   /* each of the two R-step scratch slots of sigma (default 16 GiB):
                               a smaller budget splits sigma into more launches */
   size_t t_budget_bytes;   /* renormalization scratch per growth step (default 2 GiB) */
+  int64_t ksplit_tiles;    /* sigma's L-step tasks whose k loop is longer than this many
+                              k tiles of 32 are split into about equal parts, run as
+                              separate jobs and added into sigma, one part after the
+                              other, at the end of their launch (default 512; sigma
+                              changes with it by rounding only, and never with the
+                              launch shape) */
 } dmrg_build_opts;
 
 /* Build the renormalized operators of the two-dot problem at mps->bond by
@@ -231,8 +237,8 @@ int dmrg_sigma_batched(dmrg_ctx* ctx, int nprob, dmrg_ops* const* ops,
                        const double* const* psi, double* const* sigma, int precision, int flags);
 
 /* Autotune the launch shapes of dmrg_sigma in one precision: every tile shape
- * (64x64, 32x32, 64x32, 32x64 outputs per workgroup, and the mixed shape of
- * dmrg_launch_shape), each with one workgroup per job and with dynamic units
+ * of dmrg_launch_shape (64x64, 32x32, 64x32, 32x64, mixed, 128x128, big),
+ * each with one workgroup per job and with dynamic units
  * (grid_per_xcd -1), is timed per launch on one sigma call, and the fastest is kept
  * for later calls (results do not change).  Synchronous.  ms_default /
  * ms_tuned (may be NULL) receive the summed launch times with the default
@@ -242,7 +248,10 @@ int dmrg_autotune(dmrg_ctx* ctx, dmrg_ops* ops, int precision, double* ms_defaul
 /* Launch shapes of dmrg_sigma in one precision, set by hand (what the
  * autotuner otherwise chooses): tile 0 = 64x64, 1 = 32x32, 2 = 64x32,
  * 3 = 32x64 outputs per workgroup, 4 = mixed (64x64 interior, 32-wide strips
- * for at most 32 rows or columns left over, per task); grid_per_xcd > 0 caps
+ * for at most 32 rows or columns left over, per task), 5 = 128x128 outputs
+ * per 1024-thread workgroup, 6 = big (the 128x128-tiled interiors of tasks
+ * with long k loops in one launch of 1024-thread workgroups, then everything
+ * else cut as in 4 in a second launch); grid_per_xcd > 0 caps
  * the workgroups per XCD (persistent, jobs dealt round robin), 0 = one
  * workgroup per job, -1 = dynamic: the workgroups that fit on the chip at
  * once take cost-balanced ranges of jobs from a per-XCD counter.  Other

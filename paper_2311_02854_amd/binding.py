@@ -40,7 +40,7 @@ class Mps(C.Structure):
 
 
 class BuildOpts(C.Structure):
-    _fields_ = [("x_budget_bytes", C.c_size_t), ("t_budget_bytes", C.c_size_t)]
+    _fields_ = [("x_budget_bytes", C.c_size_t), ("t_budget_bytes", C.c_size_t), ("ksplit_tiles", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -145,9 +145,9 @@ class Context:
         except Exception:
             pass
 
-    def build_ops(self, ints, mps, x_budget=0, t_budget=0):
-        """ints: dict(K, h, eri, ecore); mps: synth.SiteMPS (host arrays, copied); budgets in bytes
-        (0: library default)."""
+    def build_ops(self, ints, mps, x_budget=0, t_budget=0, ksplit_tiles=0):
+        """ints: dict(K, h, eri, ecore); mps: synth.SiteMPS (host arrays, copied); budgets in bytes,
+        ksplit_tiles the split-k threshold of sigma's L-step (0: library defaults)."""
         h = np.ascontiguousarray(ints["h"], dtype=np.float64)
         eri = np.ascontiguousarray(ints["eri"], dtype=np.float64)
         I = Integrals(int(ints["K"]), _p(h, C.c_double), _p(eri, C.c_double), float(ints.get("ecore", 0.0)))
@@ -159,7 +159,7 @@ class Context:
         M = Mps(mps.K, mps.Na, mps.Nb, mps.k, _p(nsec, C.c_int), _p(qn, C.c_int), _p(dim, C.c_int),
                 _p(off, C.c_int64), _p(data, C.c_double))
         out = C.c_void_p()
-        bo = BuildOpts(int(x_budget), int(t_budget))
+        bo = BuildOpts(int(x_budget), int(t_budget), int(ksplit_tiles))
         self._check(self.lib.dmrg_build_ops(self.h, C.byref(I), C.byref(M), C.byref(bo), C.byref(out)))
         return Ops(self, out)
 

@@ -78,6 +78,11 @@ std::unique_ptr<BatchPlan> build_batch(const std::vector<Ops*>& ops, int prec, v
         c.b_buf = remap(c.b_buf, b, pi, si);
         c.s_buf = remap(c.s_buf, b, pi, si);
       }
+      g.reduce = src.reduce;
+      for (ReduceSeg& r : g.reduce) {
+        r.dst_buf = remap(r.dst_buf, b, pi, si);
+        r.src_buf = remap(r.src_buf, b, pi, si);
+      }
       parts.push_back(std::move(g));
     }
     std::vector<GemmList*> pp;

@@ -84,6 +84,8 @@ int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mp
     dmrg::BuildOptions opt;
     if (opts && opts->x_budget_bytes) opt.x_budget = opts->x_budget_bytes;
     if (opts && opts->t_budget_bytes) opt.t_budget = opts->t_budget_bytes;
+    if (opts && opts->ksplit_tiles) opt.ksplit_tiles = opts->ksplit_tiles;
+    DMRG_CHECK(opt.ksplit_tiles > 0, DMRG_EINVAL, "ksplit_tiles must be positive");
     DMRG_CHECK(opt.x_budget >= (size_t(1) << 20) && opt.t_budget >= (size_t(1) << 20), DMRG_EINVAL,
                "scratch budgets below 1 MiB");
     auto o = dmrg::build_ops(I, K, mps->n_alpha, mps->n_beta, mps->bond, mps->nsec, mps->sec_qn, mps->sec_dim,

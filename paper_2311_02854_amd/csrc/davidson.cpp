@@ -106,14 +106,14 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     std::vector<double> Gm((size_t)m * m);
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < m; ++j) Gm[i * m + j] = G[i * 32 + j];
-    dev_h2d(dG, Gm.data(), Gm.size() * sizeof(double));
+    dev_h2d_on(dG, Gm.data(), Gm.size() * sizeof(double), stream);
     k_small_eigh(dG, m, m, dw, dZ, stream);
     std::vector<double> wv(m), Zm((size_t)m * m);
     dev_d2h(wv.data(), dw, sizeof(double) * m, stream);
     dev_d2h(Zm.data(), dZ, sizeof(double) * m * m, stream);
     theta = wv[0];
     for (int i = 0; i < m; ++i) y[i] = Zm[i * m + 0];
-    dev_h2d(dy, y.data(), sizeof(double) * m);
+    dev_h2d_on(dy, y.data(), sizeof(double) * m, stream);
     k_lincomb(V.p, n, m, dy, n, x.p, stream);
     k_lincomb(W.p, n, m, dy, n, hx.p, stream);
     k_copy(hx.p, r.p, n, stream);
@@ -151,7 +151,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       if (have_prev) {
         std::vector<double> yp(m, 0.0);
         for (int i = 0; i < m - 1; ++i) yp[i] = yprev[i];
-        dev_h2d(dy, yp.data(), sizeof(double) * m);
+        dev_h2d_on(dy, yp.data(), sizeof(double) * m, stream);
         k_lincomb(V.p, n, m, dy, n, xp.p, stream);
       }
       k_copy(x.p, Vp(0), n, stream);
@@ -183,7 +183,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
     // correction vector
     // shifted Ritz value of the preconditioner (the learned one sees it too)
     const double theta_pc = theta - opt.precond_shift * rn;
-    dev_h2d(dth, &theta_pc, sizeof(double));
+    dev_h2d_on(dth, &theta_pc, sizeof(double), stream);
     if (hook) hook(x.p, r.p, dg.p, dth, V.p, m, iters);
     used_mlp = opt.precond == 1 && mlp_fail < 3;
     if (used_mlp)
@@ -197,7 +197,7 @@ int davidson_run(Ops& O, double* psi, const dmrg_davidson_opts& opt, double* ene
       if (have_prev) {
         std::vector<double> yp(m, 0.0);
         for (int i = 0; i < m - 1; ++i) yp[i] = yprev[i];
-        dev_h2d(dy, yp.data(), sizeof(double) * m);
+        dev_h2d_on(dy, yp.data(), sizeof(double) * m, stream);
         k_lincomb(V.p, n, m, dy, n, xp.p, stream);
         k_lincomb(W.p, n, m, dy, n, hxp.p, stream);
       }

@@ -54,15 +54,30 @@ enum : int32_t { GF_TRANS_A = 1, GF_TRANS_B = 2, GF_IDENT_A = 4 };
 // GTask::accumulate bits: add to the existing C; C is binary64 whatever the
 // operand precision (the sigma output; buffer 1 always is)
 enum : int32_t { GT_ACCUM = 1, GT_C64 = 2 };
-// Workgroup tile shapes of the grouped GEMM (rows x columns of C)
-// (larger tiles, 64x128 up to 128x128, were measured slower on this GPU:
-// their register tiles drop the occupancy to 1-2 waves per SIMD)
+// Workgroup tile shapes of the grouped GEMM (rows x columns of C).  The
+// 64- and 32-wide shapes run on 256-thread workgroups (four per CU); a
+// 128 x 128 tile held by one 256-thread workgroup needs so many registers
+// that the occupancy drops to 1-2 waves per SIMD, so TILE_128 runs on
+// 1024-thread workgroups whose sixteen waves hold the 64 x 64 path's
+// per-wave sub-tiles (one workgroup per CU).
 // TILE_EDGE: every task is cut into its 64x64-tiled interior and, where the
 // rows or columns left over number at most 32, a 32x64 bottom strip, a 64x32
 // right strip and a 32x32 corner, all in one launch (per-task shape).
-enum : int { TILE_64x64 = 0, TILE_32x32 = 1, TILE_64x32 = 2, TILE_32x64 = 3, TILE_EDGE = 4, NTILE = 5 };
-inline int tile_rows(int t) { return (t == TILE_32x32 || t == TILE_32x64) ? 32 : 64; }
-inline int tile_cols(int t) { return (t == TILE_32x32 || t == TILE_64x32) ? 32 : 64; }
+// TILE_BIG: tasks with long k loops keep their 128x128-tiled interior in a
+// TILE_128 launch; the rest of them and every other task are cut as in
+// TILE_EDGE and run in a second launch right after it.
+enum : int {
+  TILE_64x64 = 0,
+  TILE_32x32 = 1,
+  TILE_64x32 = 2,
+  TILE_32x64 = 3,
+  TILE_EDGE = 4,
+  TILE_128 = 5,
+  TILE_BIG = 6,
+  NTILE = 7
+};
+inline int tile_rows(int t) { return t == TILE_128 ? 128 : (t == TILE_32x32 || t == TILE_32x64) ? 32 : 64; }
+inline int tile_cols(int t) { return t == TILE_128 ? 128 : (t == TILE_32x32 || t == TILE_64x32) ? 32 : 64; }
 
 struct GContrib {
   int32_t K;
@@ -74,6 +89,16 @@ struct GContrib {
   int64_t a_off, b_off, s_off;
   int64_t a_bstride, b_bstride, s_bstride;
   int64_t a_rstride, b_rstride, s_rstride;
+};
+
+// Reduction of split-k partial outputs (binary64):
+//   dst[dst_off + e] += src[src_off + e] + src[src_off + stride + e] + ...
+// over nsrc partials added one after the other, e < n.  Buffer ids as in
+// GTask (1 is the per-launch p1).
+struct ReduceSeg {
+  int32_t dst_buf, src_buf;
+  int32_t nsrc, pad_;
+  int64_t dst_off, src_off, src_stride, n;
 };
 
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
@@ -93,7 +118,10 @@ void host_free_pinned(void* p);
 // asynchronous copy on `stream` from page-locked host memory
 void dev_h2d_async(void* dst, const void* pinned_src, size_t bytes, void* stream);
 void dev_free(void* p);
-void dev_h2d(void* dst, const void* src, size_t bytes);            // synchronous
+void dev_h2d(void* dst, const void* src, size_t bytes);            // synchronous (complete on return)
+// synchronous copy ordered on `stream`: after the work queued there before it,
+// complete on return (for buffers that kernels on that stream read)
+void dev_h2d_on(void* dst, const void* src, size_t bytes, void* stream);
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream);  // synchronous
 void dev_sync(void* stream);
 void dev_check(const char* where);      // throws Error(EHIP) on a pending error
@@ -128,6 +156,9 @@ void graph_destroy(void* exec);
 void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
                  const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, int tile,
                  int64_t grid_per_xcd, void* stream);
+// The segments segs_dev[0 .. nseg) of a split-k reduction (device memory),
+// in one launch; segments must not write the same elements.
+void reduce_launch(const ReduceSeg* segs_dev, int nseg, void* const* table_dev, void* p1, void* stream);
 
 void k_fill(double* x, double v, int64_t n, void* stream);
 void k_zero_bytes(void* p, size_t bytes, void* stream);  // p 8-byte aligned

@@ -203,11 +203,14 @@ struct Arena {
 // shape, splits them into pieces and assigns the pieces to XCDs.  One device
 // copy per tile shape can be kept (they share the contribution array).
 class GemmList {
+  struct Dev;  // one device copy of the lists (defined below)
+
  public:
   int tile = TILE_64x64;       // shape used by run()
   int64_t grid_per_xcd = 0;    // > 0: persistent launch with this many workgroups per XCD; < 0: dynamic units
   std::vector<GTask> tasks;
   std::vector<GContrib> contribs;
+  std::vector<ReduceSeg> reduce;  // split-k partials added after the GEMM launch(es)
   int64_t njobs = 0;           // jobs at 64x64 tiles (for reporting)
   double flops = 0;
   int64_t ngemm = 0;
@@ -224,6 +227,11 @@ class GemmList {
       grid_per_xcd = o.grid_per_xcd;
       tasks = std::move(o.tasks);
       contribs = std::move(o.contribs);
+      reduce = std::move(o.reduce);
+      dreduce_ = o.dreduce_;
+      o.dreduce_ = nullptr;
+      nreduce_dev_ = o.nreduce_dev_;
+      o.nreduce_dev_ = 0;
       njobs = o.njobs;
       flops = o.flops;
       ngemm = o.ngemm;
@@ -234,6 +242,10 @@ class GemmList {
         dev_[t] = o.dev_[t];
         o.dev_[t] = Dev{};
       }
+      rest_ = o.rest_;
+      o.rest_ = Dev{};
+      big_uploaded_ = o.big_uploaded_;
+      o.big_uploaded_ = false;
     }
     return *this;
   }
@@ -312,6 +324,7 @@ class GemmList {
         refs.push_back({p, t, job_cost(p->tasks[t], p->contribs.data(), TILE_64x64)});
       m.flops += p->flops;
       m.ngemm += p->ngemm;
+      m.reduce.insert(m.reduce.end(), p->reduce.begin(), p->reduce.end());
     }
     std::stable_sort(refs.begin(), refs.end(), [](const Ref& a, const Ref& b) { return a.cost > b.cost; });
     for (const Ref& r : refs) {
@@ -328,45 +341,65 @@ class GemmList {
     return m;
   }
 
+  // Task t restricted to rows [m0, m0 + M) and columns [n0, n0 + N) of its
+  // output, with tile shape `shape`: the contributions (appended to cx) read
+  // their operands from the region's first row and column on.
+  static GTask region(const GTask& t, const GContrib* cs, int m0, int n0, int M, int N, int shape,
+                      std::vector<GContrib>& cx) {
+    GTask g = t;
+    g.M = M;
+    g.N = N;
+    g.shape = shape;
+    g.c_off = t.c_off + (int64_t)m0 * t.ldc + n0;
+    g.contrib_begin = (int32_t)cx.size();
+    for (int i = t.contrib_begin; i < t.contrib_end; ++i) {
+      GContrib c = cs[i];
+      const bool ta = c.flags & GF_TRANS_A, tb = c.flags & GF_TRANS_B;
+      if (c.flags & GF_IDENT_A) {
+        c.b_off += tb ? (int64_t)n0 * c.ldb + m0 : (int64_t)m0 * c.ldb + n0;
+      } else {
+        c.a_off += ta ? (int64_t)m0 : (int64_t)m0 * c.lda;
+        c.b_off += tb ? (int64_t)n0 * c.ldb : (int64_t)n0;
+      }
+      cx.push_back(c);
+    }
+    g.contrib_end = (int32_t)cx.size();
+    return g;
+  }
+
   // Split every task for TILE_EDGE: the interior (rows and columns in whole
   // 64-tiles, plus a last partial 64-tile when more than 32 of it are used)
   // with 64x64 tiles, the rows left over (at most 32) with 32x64 tiles, the
   // columns left over with 64x32 tiles and the corner with 32x32 tiles.  The
-  // regions write disjoint parts of C; each carries the task's contributions
-  // with the operand offsets moved to its first row and column.
-  void split_edges(std::vector<GTask>& out, std::vector<GContrib>& cx) const {
-    for (const GTask& t : tasks) {
+  // regions write disjoint parts of C.
+  static void split_edges(const std::vector<GTask>& in, const GContrib* cs, std::vector<GTask>& out,
+                          std::vector<GContrib>& cx) {
+    for (const GTask& t : in) {
       const int rm = t.M % 64, rn = t.N % 64;
       const int Mi = (rm > 0 && rm <= 32) ? t.M - rm : t.M, Ni = (rn > 0 && rn <= 32) ? t.N - rn : t.N;
       const int reg[4][5] = {{0, 0, Mi, Ni, TILE_64x64},
                              {Mi, 0, t.M - Mi, Ni, TILE_32x64},
                              {0, Ni, Mi, t.N - Ni, TILE_64x32},
                              {Mi, Ni, t.M - Mi, t.N - Ni, TILE_32x32}};
-      for (const auto& r : reg) {
-        const int m0 = r[0], n0 = r[1], M = r[2], N = r[3];
-        if (M <= 0 || N <= 0) continue;
-        GTask g = t;
-        g.M = M;
-        g.N = N;
-        g.shape = r[4];
-        g.c_off = t.c_off + (int64_t)m0 * t.ldc + n0;
-        g.contrib_begin = (int32_t)cx.size();
-        for (int i = t.contrib_begin; i < t.contrib_end; ++i) {
-          GContrib c = contribs[i];
-          const bool ta = c.flags & GF_TRANS_A, tb = c.flags & GF_TRANS_B;
-          if (c.flags & GF_IDENT_A) {
-            c.b_off += tb ? (int64_t)n0 * c.ldb + m0 : (int64_t)m0 * c.ldb + n0;
-          } else {
-            c.a_off += ta ? (int64_t)m0 : (int64_t)m0 * c.lda;
-            c.b_off += tb ? (int64_t)n0 * c.ldb : (int64_t)n0;
-          }
-          cx.push_back(c);
-        }
-        g.contrib_end = (int32_t)cx.size();
-        out.push_back(g);
-      }
+      for (const auto& r : reg)
+        if (r[2] > 0 && r[3] > 0) out.push_back(region(t, cs, r[0], r[1], r[2], r[3], r[4], cx));
     }
   }
+
+  // Rows (or columns) of a task covered by 128-tiles in TILE_BIG: the whole
+  // 128-tiles, plus a last partial one when more than 96 of it are used.
+  static int big_extent(int n) { return (n / 128) * 128 + (n % 128 > 96 ? n % 128 : 0); }
+  // k tiles (of 32) of one job of task t: its MFMA contributions
+  static int64_t k_tiles(const GTask& t, const GContrib* cs) {
+    int64_t kt = 0;
+    for (int i = t.contrib_begin; i < t.contrib_end; ++i)
+      if (!(cs[i].flags & GF_IDENT_A)) kt += (int64_t)cs[i].nred * ((cs[i].K + 31) / 32);
+    return kt;
+  }
+  // TILE_BIG: tasks whose jobs run at least this many k tiles keep their
+  // 128-tiled interior in the TILE_128 launch (short k loops stay with the
+  // 256-thread shapes, which overlap four workgroups per CU)
+  static constexpr int64_t BIG_MIN_KTILES = 32;
 
   // Count tiles for shape tl, split tasks into job-range pieces, assign them
   // to XCDs (longest processing time first) and upload the per-XCD lists:
@@ -375,9 +408,24 @@ class GemmList {
   void upload(int tl, Arena* arena = nullptr, UploadRing* ring = nullptr) {
     DMRG_CHECK(tl >= 0 && tl < NTILE, DMRG_EINVAL, "unknown tile shape");
     free_dev(dev_[tl]);
+    if (tl == TILE_BIG) {
+      free_dev(rest_);
+      big_uploaded_ = false;
+    }
     if (tasks.empty()) return;
-    Dev& D = dev_[tl];
-    D.external = arena != nullptr || ring != nullptr;
+    if (!reduce.empty() && !dreduce_) {
+      DMRG_CHECK(!arena && !ring, DMRG_EINTERNAL, "split-k reduction in an allocation-free list");
+      dreduce_ = (ReduceSeg*)dev_alloc_nozero(reduce.size() * sizeof(ReduceSeg));
+      dev_h2d(dreduce_, reduce.data(), reduce.size() * sizeof(ReduceSeg));
+      nreduce_dev_ = (int)reduce.size();
+    }
+    // the kernel addresses one k tile of an operand with 32-bit byte offsets
+    // from its first element: at most 128 rows (or 32 k) of the leading
+    // dimension, which must stay below 2^21 elements
+    for (const GContrib& c : contribs)
+      DMRG_CHECK(c.lda < (1 << 21) && c.ldb < (1 << 21), DMRG_ESHAPE,
+                 "GEMM leading dimension too large for 32-bit tile offsets (limit 2^21 elements)");
+    const bool external = arena != nullptr || ring != nullptr;
     // device copy of a host array: a fresh allocation, the arena, or the ring
     auto put = [&](const void* src, size_t b) -> void* {
       if (ring) return ring->stage(src, b);  // one copy for the whole list (flushed below)
@@ -385,32 +433,66 @@ class GemmList {
       dev_h2d(p, src, b);
       return p;
     };
-    std::vector<GTask> src;
-    std::vector<GContrib> cx;
-    const GContrib* cs = contribs.data();
-    if (tl == TILE_EDGE) {
-      split_edges(src, cx);
-      cs = cx.data();
+    auto own_contribs = [&](Dev& D, const std::vector<GContrib>& cx) {
       D.contribs = (GContrib*)put(cx.data(), cx.size() * sizeof(GContrib));
       D.ncontribs = cx.size();
+    };
+    if (tl == TILE_EDGE) {
+      std::vector<GTask> src;
+      std::vector<GContrib> cx;
+      split_edges(tasks, contribs.data(), src, cx);
+      Dev& D = dev_[tl];
+      D.external = external;
+      own_contribs(D, cx);
+      map_and_put(D, src, cx.data(), put);
+    } else if (tl == TILE_BIG) {
+      std::vector<GTask> big, rest_in, rest;
+      std::vector<GContrib> cbig, crest_in, crest;
+      const GContrib* cs = contribs.data();
+      for (const GTask& t : tasks) {
+        const int Mi = big_extent(t.M), Ni = big_extent(t.N);
+        if (Mi > 0 && Ni > 0 && k_tiles(t, cs) >= BIG_MIN_KTILES) {
+          big.push_back(region(t, cs, 0, 0, Mi, Ni, TILE_128, cbig));
+          if (t.M > Mi) rest_in.push_back(region(t, cs, Mi, 0, t.M - Mi, t.N, TILE_64x64, crest_in));
+          if (t.N > Ni) rest_in.push_back(region(t, cs, 0, Ni, Mi, t.N - Ni, TILE_64x64, crest_in));
+        } else {
+          rest_in.push_back(region(t, cs, 0, 0, t.M, t.N, TILE_64x64, crest_in));
+        }
+      }
+      split_edges(rest_in, crest_in.data(), rest, crest);
+      Dev& D = dev_[tl];
+      D.external = rest_.external = external;
+      if (!big.empty()) {
+        own_contribs(D, cbig);
+        map_and_put(D, big, cbig.data(), put);
+      }
+      if (!rest.empty()) {
+        own_contribs(rest_, crest);
+        map_and_put(rest_, rest, crest.data(), put);
+      }
+      big_uploaded_ = true;
     } else {
-      src = tasks;
+      std::vector<GTask> src = tasks;
       for (GTask& g : src) g.shape = tl;
-      if (D.external) {  // own copy of the contributions, in the arena or ring
-        D.contribs = (GContrib*)put(contribs.data(), contribs.size() * sizeof(GContrib));
-        D.ncontribs = contribs.size();
+      Dev& D = dev_[tl];
+      D.external = external;
+      if (external) {  // own copy of the contributions, in the arena or ring
+        own_contribs(D, contribs);
       } else if (!dcontribs_) {
         dcontribs_ = (GContrib*)dev_alloc((contribs.size() + 1) * sizeof(GContrib));
         if (!contribs.empty()) dev_h2d(dcontribs_, contribs.data(), contribs.size() * sizeof(GContrib));
         ncontribs_dev_ = contribs.size();
       }
+      map_and_put(D, src, contribs.data(), put);
     }
-    // the kernel addresses one k tile of an operand with 32-bit byte offsets
-    // from its first element: at most 64 rows (or 32 k) of the leading
-    // dimension, which must stay below 2^21 elements
-    for (const GContrib& c : contribs)
-      DMRG_CHECK(c.lda < (1 << 21) && c.ldb < (1 << 21), DMRG_ESHAPE,
-                 "GEMM leading dimension too large for 32-bit tile offsets (limit 2^21 elements)");
+    if (ring) ring->flush();
+  }
+
+  // Split the tasks of one device list (each with its tile shape) into
+  // job-range pieces, assign them to XCDs (longest processing time first),
+  // and put the per-XCD task lists, bucket table and dynamic units.
+  template <class Put>
+  static void map_and_put(Dev& D, const std::vector<GTask>& src, const GContrib* cs, Put&& put) {
     std::memset(&D.map, 0, sizeof(D.map));
     std::vector<GTask> dev;
     std::vector<double> cj(src.size());
@@ -448,7 +530,9 @@ class GemmList {
     }
     // Units for dynamic launches (guided self-scheduling): a unit of
     // consecutive jobs takes about 1/(4 S) of the work left on its XCD, with
-    // S = 128 workgroups per XCD, and at least one job.
+    // S the workgroups resident per XCD (128 of the 256-thread shapes, 32 of
+    // TILE_128), and at least one job.
+    const double S = (!src.empty() && src[0].shape == TILE_128) ? 32.0 : 128.0;
     std::vector<int64_t> units;
     for (int x = 0; x < NXCD; ++x) {
       // longest jobs first inside an XCD
@@ -459,7 +543,7 @@ class GemmList {
       int64_t jb = 0;
       for (const Piece& p : per[x]) {
         for (int64_t left = p.n, j = jb; left > 0;) {
-          const double target = std::max(p.c, rem / (4.0 * 128));
+          const double target = std::max(p.c, rem / (4.0 * S));
           const int64_t g = std::max<int64_t>(1, std::min<int64_t>(left, (int64_t)(target / p.c)));
           units.push_back(j);
           j += g;
@@ -503,41 +587,62 @@ class GemmList {
     D.map.bucket_begin[NXCD] = (int)bucket.size();
     D.bucket = (int*)put(bucket.data(), bucket.size() * sizeof(int));
     D.tasks = (GTask*)put(dev.data(), dev.size() * sizeof(GTask));
-    if (ring) ring->flush();
     D.ntasks = (int)dev.size();
   }
   void upload() { upload(tile); }
-  bool uploaded(int tl) const { return dev_[tl].tasks != nullptr || tasks.empty(); }
+  bool uploaded(int tl) const {
+    return tasks.empty() || (tl == TILE_BIG ? big_uploaded_ : dev_[tl].tasks != nullptr);
+  }
   void run(DevTable& tab, const void* p0, void* p1, int elem, void* stream) { run_tile(tile, tab, p0, p1, elem, stream); }
   void run_tile(int tl, DevTable& tab, const void* p0, void* p1, int elem, void* stream) {
-    if (!dev_[tl].tasks) upload(tl);
+    if (!uploaded(tl)) upload(tl);
     run_uploaded(tl, tab.device(), p0, p1, elem, stream);
   }
   // launch the lists uploaded for shape tl with a device pointer table
   void run_uploaded(int tl, void* const* table_dev, const void* p0, void* p1, int elem, void* stream) {
-    const Dev& D = dev_[tl];
-    if (D.ntasks == 0) return;
-    gemm_launch(D.tasks, D.ntasks, D.map, D.contribs ? D.contribs : dcontribs_, D.bucket, table_dev, p0, p1, elem,
-                tl, grid_per_xcd, stream);
+    auto launch = [&](const Dev& D, int shape) {
+      if (D.ntasks == 0) return;
+      gemm_launch(D.tasks, D.ntasks, D.map, D.contribs ? D.contribs : dcontribs_, D.bucket, table_dev, p0, p1, elem,
+                  shape, grid_per_xcd, stream);
+    };
+    if (tl == TILE_BIG) {  // the 128x128 interiors, then everything else
+      launch(dev_[TILE_BIG], TILE_128);
+      launch(rest_, TILE_EDGE);
+    } else {
+      launch(dev_[tl], tl);
+    }
+    if (nreduce_dev_) reduce_launch(dreduce_, nreduce_dev_, table_dev, p1, stream);
   }
   void release() {
     for (int t = 0; t < NTILE; ++t) free_dev(dev_[t]);
+    free_dev(rest_);
+    big_uploaded_ = false;
+    dev_free(dreduce_);
+    dreduce_ = nullptr;
+    nreduce_dev_ = 0;
     dev_free(dcontribs_);
     dcontribs_ = nullptr;
     ncontribs_dev_ = 0;
   }
   // drop the device copy of one tile shape (rebuilt on demand from the host list)
   void release_tile(int t) {
-    if (!tasks.empty()) free_dev(dev_[t]);
+    if (tasks.empty()) return;
+    free_dev(dev_[t]);
+    if (t == TILE_BIG) {
+      free_dev(rest_);
+      big_uploaded_ = false;
+    }
   }
   void clear_host() {
     std::vector<GTask>().swap(tasks);
     std::vector<GContrib>().swap(contribs);
+    std::vector<ReduceSeg>().swap(reduce);
   }
   size_t host_bytes() const { return tasks.size() * sizeof(GTask) + contribs.size() * sizeof(GContrib); }
   size_t device_bytes() const {
     size_t b = ncontribs_dev_ * sizeof(GContrib);
     for (int t = 0; t < NTILE; ++t) b += (size_t)dev_[t].ntasks * sizeof(GTask) + dev_[t].ncontribs * sizeof(GContrib);
+    b += (size_t)rest_.ntasks * sizeof(GTask) + rest_.ncontribs * sizeof(GContrib);
     return b;
   }
 
@@ -568,11 +673,15 @@ class GemmList {
   bool any_dev() const {
     for (int t = 0; t < NTILE; ++t)
       if (dev_[t].ntasks) return true;
-    return false;
+    return rest_.ntasks != 0;
   }
   GContrib* dcontribs_ = nullptr;
   size_t ncontribs_dev_ = 0;
   Dev dev_[NTILE];
+  Dev rest_;                  // TILE_BIG: the launch after the 128x128 interiors
+  bool big_uploaded_ = false;
+  ReduceSeg* dreduce_ = nullptr;
+  int nreduce_dev_ = 0;
 };
 
 inline GContrib make_contrib(int K, int flags, int a_buf, int64_t a_off, int lda, int b_buf, int64_t b_off,

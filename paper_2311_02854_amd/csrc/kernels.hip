@@ -76,7 +76,10 @@ void* dev_alloc(size_t bytes) {
     (void)hipGetLastError();
     throw Error(DMRG_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
   }
+  // the fill runs on the null stream, which work on non-blocking streams does
+  // not wait for: wait for it here
   HIPCHK(hipMemset(p, 0, bytes));
+  HIPCHK(hipStreamSynchronize(nullptr));
   return p;
 }
 
@@ -114,7 +117,17 @@ void dev_h2d_async(void* dst, const void* src, size_t bytes, void* stream) {
 }
 
 void dev_h2d(void* dst, const void* src, size_t bytes) {
-  if (bytes) HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+  if (!bytes) return;
+  // a copy from pageable memory may return before its DMA has landed, and
+  // kernels on non-blocking streams do not wait for the null stream
+  HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+  HIPCHK(hipStreamSynchronize(nullptr));
+}
+
+void dev_h2d_on(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!bytes) return;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, S(stream)));
+  HIPCHK(hipStreamSynchronize(S(stream)));
 }
 
 void dev_d2h(void* dst, const void* src, size_t bytes, void* stream) {
@@ -180,7 +193,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int BK = 32, NT = 256;
+constexpr int BK = 32, NT = 256, NT_BIG = 1024;
 
 // Operand precision policies.  FP64 and FP32 stage op(A) and op(B) tiles in
 // LDS k-major ([k][row], rows contiguous) and feed 16x16x4 MFMAs one element
@@ -213,8 +226,7 @@ struct PolBF3 {
   static constexpr int RL = 4, RV = 1;
 };
 
-// Tile shape: the four waves form a 2 x 2 grid, each wave owns WM x WN
-// sub-tiles of 16 x 16, so the workgroup tile is (32 WM) x (32 WN).
+// LDS staging of one k tile of op(A) (BM_ rows) and op(B) (BN_ columns).
 template <class P, int BM_, int BN_, bool S = P::split>
 struct alignas(16) Smem {
   typename P::T A[BK][BM_ + P::PAD];
@@ -278,10 +290,11 @@ __device__ __forceinline__ int find_task(const GTask* __restrict__ tasks, const 
   return lo;
 }
 
-// Per-thread view of one ROWS x BK operand tile: element (r, k) of op(X) sits
-// at X + r*sr + k*sk.  When k is contiguous (kc: sk == 1) threads walk k
-// fastest (32 per row, 8 rows per pass), otherwise r fastest (ROWS per row,
-// 256/ROWS k per pass); either way every thread owns E = ROWS*BK/256 elements.
+// Per-thread view of one ROWS x BK operand tile staged by NTH threads: element
+// (r, k) of op(X) sits at X + r*sr + k*sk.  When k is contiguous (kc: sk == 1)
+// threads walk k fastest (32 per row, NTH/32 rows per pass), otherwise r
+// fastest (ROWS per row, NTH/ROWS k per pass); either way every thread owns
+// E = ROWS*BK/NTH elements.
 //
 // Loads go through a buffer descriptor based at the k tile's first element
 // whose range ends at the operand's last valid element among the tile's rows:
@@ -328,7 +341,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const Opnd<T>& o, in
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(o.origin + kb), (short)0, (int)rem, 0x00020000);
 }
 
-template <int ROWS, typename T>
+template <int ROWS, int NTH, typename T>
 __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, int64_t sk, int r0, int rows,
                                            int K, T scale) {
   const int tid = threadIdx.x;
@@ -336,15 +349,15 @@ __device__ __forceinline__ void opnd_setup(Opnd<T>& o, const T* X, int64_t sr, i
   if (sk == 1) {
     r_first = tid >> 5;
     k_first = tid & 31;
-    o.r_inc = 8;
+    o.r_inc = NTH / 32;
     o.k_inc = 0;
-    o.step_it = (int32_t)(8 * sr * (int64_t)sizeof(T));
+    o.step_it = (int32_t)((NTH / 32) * sr * (int64_t)sizeof(T));
   } else {
     r_first = tid % ROWS;
     k_first = tid / ROWS;
     o.r_inc = 0;
-    o.k_inc = NT / ROWS;
-    o.step_it = (int32_t)((NT / ROWS) * sk * (int64_t)sizeof(T));
+    o.k_inc = NTH / ROWS;
+    o.step_it = (int32_t)((NTH / ROWS) * sk * (int64_t)sizeof(T));
   }
   o.origin = reinterpret_cast<const char*>(X + (int64_t)r0 * sr);
   o.range = tile_range<ROWS, T>(sr, sk, rows - r0, K);
@@ -370,30 +383,30 @@ __device__ __forceinline__ void opnd_load(const Opnd<T>& o, int k0, T (&v)[E]) {
 // Element it of a thread's share of a ROWS x BK tile sits at (row, k) =
 // (r_first + it*r_inc, k_first + it*k_inc), with the pattern opnd_setup
 // picks for k-contiguous (kc) or row-contiguous operands.
-template <int ROWS>
+template <int ROWS, int NTH>
 __device__ __forceinline__ void tile_pattern(bool kc, int& r_first, int& k_first, int& r_inc, int& k_inc) {
   const int tid = threadIdx.x;
   r_first = kc ? tid >> 5 : tid % ROWS;
   k_first = kc ? tid & 31 : tid / ROWS;
-  r_inc = kc ? 8 : 0;
-  k_inc = kc ? 0 : NT / ROWS;
+  r_inc = kc ? NTH / 32 : 0;
+  k_inc = kc ? 0 : NTH / ROWS;
 }
 
 // kvalid: valid k of this tile (the k tail of a kc tile is zeroed here)
-template <int ROWS, int E, typename T, int LD>
+template <int ROWS, int NTH, int E, typename T, int LD>
 __device__ __forceinline__ void opnd_store(bool kc, int kvalid, T scale, const T (&v)[E], T (*L)[LD]) {
   int r_first, k_first, r_inc, k_inc;
-  tile_pattern<ROWS>(kc, r_first, k_first, r_inc, k_inc);
+  tile_pattern<ROWS, NTH>(kc, r_first, k_first, r_inc, k_inc);
   const bool keep = !kc || k_first < kvalid;
 #pragma unroll
   for (int it = 0; it < E; ++it) L[k_first + it * k_inc][r_first + it * r_inc] = keep ? v[it] * scale : T(0);
 }
 
 // Split-BF16 staging: every thread owns E/2 pairs of k-consecutive elements
-// (k contiguous in memory: 16 threads per row, 16 rows per pass; else r
-// fastest, 2*256/ROWS k per pass), so that each pair converts with one
+// (k contiguous in memory: 16 threads per row, NTH/16 rows per pass; else r
+// fastest, 2*NTH/ROWS k per pass), so that each pair converts with one
 // instruction and lands in LDS ([row][k]) as one 32-bit store per half.
-template <int ROWS>
+template <int ROWS, int NTH>
 __device__ __forceinline__ void opnd_setup_split(Opnd<float>& o, const float* X, int64_t sr, int64_t sk, int r0,
                                                  int rows, int K, float scale) {
   const int tid = threadIdx.x;
@@ -401,15 +414,15 @@ __device__ __forceinline__ void opnd_setup_split(Opnd<float>& o, const float* X,
   if (sk == 1) {
     r_first = tid >> 4;
     k_first = 2 * (tid & 15);
-    o.r_inc = NT / 16;
+    o.r_inc = NTH / 16;
     o.k_inc = 0;
-    o.step_it = (int32_t)((NT / 16) * sr * 4);
+    o.step_it = (int32_t)((NTH / 16) * sr * 4);
   } else {
     r_first = tid % ROWS;
     k_first = 2 * (tid / ROWS);
     o.r_inc = 0;
-    o.k_inc = 2 * NT / ROWS;
-    o.step_it = (int32_t)((2 * NT / ROWS) * sk * 4);
+    o.k_inc = 2 * NTH / ROWS;
+    o.step_it = (int32_t)((2 * NTH / ROWS) * sk * 4);
   }
   o.s2 = (int32_t)(sk * 4);
   o.origin = reinterpret_cast<const char*>(X + (int64_t)r0 * sr);
@@ -429,20 +442,20 @@ __device__ __forceinline__ void opnd_load_split(const Opnd<float>& o, int k0, fl
   }
 }
 
-template <int ROWS>
+template <int ROWS, int NTH>
 __device__ __forceinline__ void tile_pattern_split(bool kc, int& r_first, int& k_first, int& r_inc, int& k_inc) {
   const int tid = threadIdx.x;
   r_first = kc ? tid >> 4 : tid % ROWS;
   k_first = kc ? 2 * (tid & 15) : 2 * (tid / ROWS);
-  r_inc = kc ? NT / 16 : 0;
-  k_inc = kc ? 0 : 2 * NT / ROWS;
+  r_inc = kc ? NTH / 16 : 0;
+  k_inc = kc ? 0 : 2 * NTH / ROWS;
 }
 
-template <int ROWS, int E, int LD>
+template <int ROWS, int NTH, int E, int LD>
 __device__ __forceinline__ void opnd_store_split(bool kc, int kvalid, float scale, const float (&v)[E],
                                                  uint16_t (*H)[LD], uint16_t (*Lo)[LD]) {
   int r_first, k_first, r_inc, k_inc;
-  tile_pattern_split<ROWS>(kc, r_first, k_first, r_inc, k_inc);
+  tile_pattern_split<ROWS, NTH>(kc, r_first, k_first, r_inc, k_inc);
   const bool keep0 = !kc || k_first < kvalid, keep1 = !kc || k_first + 1 < kvalid;
 #pragma unroll
   for (int it = 0; it < E / 2; ++it) {
@@ -461,23 +474,27 @@ struct Step {
   int K;
 };
 
-// One job of a grouped GEMM task: the tile `local` (batch-major) of task Tk
-// with a (32 WM) x (32 WN) workgroup tile.  smem holds at least
-// sizeof(Smem<P, 32 WM, 32 WN>) bytes.
-template <class P, int WM, int WN>
+// One job of a grouped GEMM task: the tile `local` (batch-major) of task Tk.
+// The NTH / 64 waves form a GW x GW grid and each wave owns WM x WN sub-tiles
+// of 16 x 16, so the workgroup tile is (16 WM GW) x (16 WN GW): 256 threads
+// in 2 x 2 waves, or 1024 threads in 4 x 4 waves (128 x 128 tiles).  smem
+// holds at least sizeof(Smem<P, BM, BN>) bytes.
+template <class P, int WM, int WN, int NTH = NT>
 __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* smem,
                                          const GContrib* __restrict__ contribs,
                                          typename P::T* const* __restrict__ table, const typename P::T* p0,
                                          double* p1) {
   using T = typename P::T;
   using Acc = typename P::Acc;
-  constexpr int BM = 32 * WM, BN = 32 * WN, EA = BM * BK / NT, EB = BN * BK / NT;
+  constexpr int GW = NTH == 1024 ? 4 : 2;
+  static_assert(NTH == 64 * GW * GW, "workgroup of 2 x 2 or 4 x 4 waves");
+  constexpr int BM = 16 * WM * GW, BN = 16 * WN * GW, EA = BM * BK / NTH, EB = BN * BK / NTH;
   Smem<P, BM, BN>& sm = *reinterpret_cast<Smem<P, BM, BN>*>(smem);
   // the wave index is uniform across its lanes: keep it (and the sub-tile
   // predicates derived from it) scalar, so that inactive sub-tiles branch
   // around their MFMAs instead of selecting whole accumulators
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
+  const int wm = (wave / GW) * 16 * WM, wn = (wave % GW) * 16 * WN;
   const int lr = lane & 15, lk = lane >> 4;
   auto opp = [&](int id) -> const T* { return id == 0 ? p0 : (id == 1 ? (const T*)p1 : table[id]); };
   {
@@ -543,11 +560,11 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
       const bool ta = Cb.flags & GF_TRANS_A, tb = Cb.flags & GF_TRANS_B;
       // op(A)(m, k): stored M x K (lda) or K x M;  op(B)(k, n) seen as (n, k)
       if constexpr (P::split) {
-        opnd_setup_split<BM>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
-        opnd_setup_split<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
+        opnd_setup_split<BM, NTH>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
+        opnd_setup_split<BN, NTH>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
       } else {
-        opnd_setup<BM>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
-        opnd_setup<BN>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
+        opnd_setup<BM, NTH>(oa, A, ta ? 1 : Cb.lda, ta ? Cb.lda : 1, m0, Tk.M, Cb.K, alpha);
+        opnd_setup<BN, NTH>(ob, B, tb ? Cb.ldb : 1, tb ? 1 : Cb.ldb, n0, Tk.N, Cb.K, T(1));
       }
     };
     // what staging a register set needs from the step it holds
@@ -593,11 +610,11 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
       };
       auto stage = [&](const T (&ra)[EA], const T (&rb)[EB], const SetMeta& m) {
         if constexpr (P::split) {
-          opnd_store_split<BM>(m.akc, m.kend, m.scale, ra, sm.Ah, sm.Al);
-          opnd_store_split<BN>(m.bkc, m.kend, T(1), rb, sm.Bh, sm.Bl);
+          opnd_store_split<BM, NTH>(m.akc, m.kend, m.scale, ra, sm.Ah, sm.Al);
+          opnd_store_split<BN, NTH>(m.bkc, m.kend, T(1), rb, sm.Bh, sm.Bl);
         } else {
-          opnd_store<BM>(m.akc, m.kend, m.scale, ra, sm.A);
-          opnd_store<BN>(m.bkc, m.kend, T(1), rb, sm.B);
+          opnd_store<BM, NTH>(m.akc, m.kend, m.scale, ra, sm.A);
+          opnd_store<BN, NTH>(m.bkc, m.kend, T(1), rb, sm.B);
         }
       };
       auto multiply = [&](int kend) {
@@ -723,6 +740,29 @@ __device__ __forceinline__ void gemm_job(const GTask& Tk, int64_t local, void* s
   }
 }
 
+// The jobs of this workgroup's XCD: units taken from the XCD's counter
+// (dynamic launches), else every gridDim.x / NXCD-th job from blockIdx.x / NXCD.
+template <class Run>
+__device__ __forceinline__ void for_each_job(const XcdMap& map, int64_t* s_unit, Run&& run) {
+  const int xcd = blockIdx.x % NXCD;
+  if (map.dynamic) {
+    const int64_t* __restrict__ U = map.units + map.unit_begin[xcd];
+    const int64_t nu = map.nunits[xcd];
+    for (;;) {
+      if (threadIdx.x == 0) *s_unit = (int64_t)atomicAdd(map.counters + 64 * xcd, 1u);
+      __syncthreads();
+      const int64_t u = *s_unit;
+      __syncthreads();
+      if (u >= nu) break;
+      const int64_t je = U[u + 1];
+      for (int64_t job = U[u]; job < je; ++job) run(job);
+    }
+  } else {
+    const int64_t njobs = map.njobs[xcd];
+    for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) run(job);
+  }
+}
+
 // Grouped GEMM over a task list (see device.h).  Operand buffers hold P::T;
 // the output is P::T, or binary64 for tasks flagged GT_C64 (buffer 1 is p1).
 // MIXED: every task carries its own tile shape (TILE_EDGE launches).
@@ -735,9 +775,8 @@ __global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ t
   using SmemT = std::conditional_t<MIXED, Smem<P, 64, 64>, Smem<P, 32 * WM, 32 * WN>>;
   __shared__ SmemT smem;
   __shared__ int64_t s_unit;
-  const int xcd = blockIdx.x % NXCD;
-  const int* __restrict__ bucket = bucket_all + map.bucket_begin[xcd];
-  auto run = [&](int64_t job) {
+  const int* __restrict__ bucket = bucket_all + map.bucket_begin[blockIdx.x % NXCD];
+  for_each_job(map, &s_unit, [&](int64_t job) {
     const GTask& Tk = tasks[find_task(tasks, bucket, map.shift, job)];
     const int64_t local = job - Tk.job_begin + Tk.job_off;
     if constexpr (!MIXED) {
@@ -758,23 +797,26 @@ __global__ __launch_bounds__(NT, 4) void gemm_kernel(const GTask* __restrict__ t
           break;
       }
     }
-  };
-  if (map.dynamic) {
-    const int64_t* __restrict__ U = map.units + map.unit_begin[xcd];
-    const int64_t nu = map.nunits[xcd];
-    for (;;) {
-      if (threadIdx.x == 0) s_unit = (int64_t)atomicAdd(map.counters + 64 * xcd, 1u);
-      __syncthreads();
-      const int64_t u = s_unit;
-      __syncthreads();
-      if (u >= nu) break;
-      const int64_t je = U[u + 1];
-      for (int64_t job = U[u]; job < je; ++job) run(job);
-    }
-  } else {
-    const int64_t njobs = map.njobs[xcd];
-    for (int64_t job = blockIdx.x / NXCD; job < njobs; job += gridDim.x / NXCD) run(job);
-  }
+  });
+}
+
+// 128 x 128 tiles on 1024-thread workgroups (TILE_128): sixteen waves, each
+// with the 32 x 32 sub-tile of the 256-thread 64 x 64 path, share one operand
+// tile in LDS, so that every operand byte fetched feeds twice the MFMA work.
+// One workgroup fills a CU (four waves per SIMD).
+template <class P>
+__global__ __launch_bounds__(NT_BIG, 1) void gemm_kernel_big(const GTask* __restrict__ tasks, const XcdMap map,
+                                                          const GContrib* __restrict__ contribs,
+                                                          const int* __restrict__ bucket_all,
+                                                          typename P::T* const* __restrict__ table,
+                                                          const typename P::T* p0, double* p1) {
+  __shared__ Smem<P, 128, 128> smem;
+  __shared__ int64_t s_unit;
+  const int* __restrict__ bucket = bucket_all + map.bucket_begin[blockIdx.x % NXCD];
+  for_each_job(map, &s_unit, [&](int64_t job) {
+    const GTask& Tk = tasks[find_task(tasks, bucket, map.shift, job)];
+    gemm_job<P, 2, 2, NT_BIG>(Tk, job - Tk.job_begin + Tk.job_off, &smem, contribs, table, p0, p1);
+  });
 }
 
 __global__ void zero_counters_kernel(unsigned* c) {
@@ -800,6 +842,9 @@ static void launch_variant(int tile, dim3 grid, hipStream_t s, const GTask* t, c
       break;
     case TILE_EDGE:
       hipLaunchKernelGGL((gemm_kernel<P, 2, 2, true>), grid, dim3(NT), 0, s, t, map, c, bk, tab, p0, p1);
+      break;
+    case TILE_128:
+      hipLaunchKernelGGL((gemm_kernel_big<P>), grid, dim3(NT_BIG), 0, s, t, map, c, bk, tab, p0, p1);
       break;
     default:
       throw Error(DMRG_EINVAL, "unknown GEMM tile shape");
@@ -835,12 +880,15 @@ static int blocks_per_cu_of(int tile) {
       case TILE_EDGE:
         f = reinterpret_cast<const void*>(&gemm_kernel<P, 2, 2, true>);
         break;
+      case TILE_128:
+        f = reinterpret_cast<const void*>(&gemm_kernel_big<P>);
+        break;
       default:
         f = reinterpret_cast<const void*>(&gemm_kernel<P, 2, 2, false>);
         break;
     }
     int nb = 0;
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, NT, 0));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, tile == TILE_128 ? NT_BIG : NT, 0));
     v = nb > 0 ? nb : 1;
     cache[dev][tile].store(v, std::memory_order_relaxed);
   }
@@ -891,6 +939,26 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
     throw Error(DMRG_EINVAL, "unknown GEMM precision");
   }
   dev_check("gemm_launch");
+}
+
+// One workgroup per (segment, slice): slice y of 8 takes every 8th run of
+// 256 elements.  The partials of an element are added in order.
+__global__ void reduce_kernel(const ReduceSeg* __restrict__ segs, void* const* __restrict__ table, double* p1) {
+  const ReduceSeg sg = segs[blockIdx.x];
+  double* dst = (sg.dst_buf == 1 ? p1 : reinterpret_cast<double*>(table[sg.dst_buf])) + sg.dst_off;
+  const double* src = (sg.src_buf == 1 ? p1 : reinterpret_cast<const double*>(table[sg.src_buf])) + sg.src_off;
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < sg.n; e += 256 * (int64_t)gridDim.y) {
+    double v = dst[e];
+    for (int s = 0; s < sg.nsrc; ++s) v += src[e + s * sg.src_stride];
+    dst[e] = v;
+  }
+}
+
+void reduce_launch(const ReduceSeg* segs_dev, int nseg, void* const* table_dev, void* p1, void* stream) {
+  if (nseg <= 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)nseg, 8), dim3(256), 0, S(stream), segs_dev, table_dev,
+                     (double*)p1);
+  dev_check("reduce_launch");
 }
 
 // ---------------------------------------------------------------- vector kernels

@@ -84,19 +84,19 @@ void mlp_prepare(Ops& O, void* stream) {
   (void)stream;
 }
 
-static void mlp_set_weights(Ops& O, const float* w) {
+static void mlp_set_weights(Ops& O, const float* w, void* stream) {
   const int nw = mlp_nweights();
   if (!O.mlp_w) O.mlp_w = (float*)dev_alloc(sizeof(float) * nw);
   if ((int)O.mlp_w_host.size() != nw || std::memcmp(O.mlp_w_host.data(), w, sizeof(float) * nw) != 0) {
     O.mlp_w_host.assign(w, w + nw);
-    dev_h2d(O.mlp_w, w, sizeof(float) * nw);
+    dev_h2d_on(O.mlp_w, w, sizeof(float) * nw, stream);  // after the applies already queued
   }
 }
 
 void mlp_precondition(Ops& O, const double* r, const double* diag, const double* theta_dev, double* t,
                       const float* weights, void* stream) {
   mlp_prepare(O, stream);
-  mlp_set_weights(O, weights);
+  mlp_set_weights(O, weights, stream);
   k_mlp_scales(r, diag, theta_dev, O.npsi, O.mlp_part, O.mlp_scales, stream);
   k_mlp_apply(O.mlp_w, r, diag, theta_dev, O.mlp_scales, O.mlp_blk, O.mlp_stat, FLOOR, t, O.npsi, stream);
 }
@@ -143,7 +143,7 @@ int64_t mlp_collect(Ops& O, const double* psi0, const double* psi_ref, int max_i
     std::uniform_int_distribution<int64_t> U(0, n - 1);
     const int m = (int)std::min<int64_t>(per_iter, cap - written);
     for (int j = 0; j < m; ++j) idx[j] = U(rng);
-    dev_h2d(didx, idx.data(), sizeof(int64_t) * m);
+    dev_h2d_on(didx, idx.data(), sizeof(int64_t) * m, stream);
     k_mlp_gather_pairs(didx, m, r, diag, theta_dev, O.mlp_scales, O.mlp_blk, O.mlp_stat, e.p, es, FLOOR, ff.p,
                        fd.p, fy.p, stream);
     // k_mlp_gather_pairs computes d_i from r; rescale it by rms(d) like the target
@@ -273,7 +273,7 @@ void mlp_train(int64_t n, const float* feat, const float* dcorr, const float* ta
       int64_t nr = 0;
       for (int u : tr)
         for (int64_t i = 0; i < usz; ++i) rows[nr++] = (int)(u * usz + i);
-      dev_h2d(drows, rows.data(), sizeof(int) * (size_t)nr);
+      dev_h2d_on(drows, rows.data(), sizeof(int) * (size_t)nr, stream);
       for (int64_t s0 = 0; s0 + B <= nr; s0 += B) {
         k_gather_rows(F.p, drows + s0, B, NF, Fb.p, stream);
         k_gather_rows(Dv.p, drows + s0, B, 1, Db.p, stream);

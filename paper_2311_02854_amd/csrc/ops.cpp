@@ -101,6 +101,7 @@ Ops::~Ops() {
   for (auto& g : extra) g->free_dev();
   dev_free(X[0]);
   dev_free(X[1]);
+  dev_free(partial);
   dev_free(X32[0]);
   dev_free(X32[1]);
   dev_free(psi32);
@@ -726,6 +727,8 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
   const int nrchunks = (int)chunk_pieces.size();
   // identity-R families form an extra chunk without an R-step
   chunk_pieces.push_back({{-1, 0, 0, 0}});
+  O.pbuf = tab.add(nullptr);  // split-k partials (allocated once the plan is sized)
+  int64_t partial_max = 0;    // doubles
 
   std::vector<GemmList> Rl(chunk_pieces.size()), Ll(chunk_pieces.size());
   for (size_t ci = 0; ci < chunk_pieces.size(); ++ci) {
@@ -803,18 +806,71 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
         }
       }
     }
+    // One task per output block.  A task whose k loop (contributions x
+    // members x k tiles) is longer than opt.ksplit_tiles is cut at member
+    // boundaries into parts of about equal length: the first part adds into
+    // sigma, the others write partial blocks that the launch's reduction then
+    // adds into sigma one after the other.  Every launch shape sees the same
+    // parts, so results stay the same across shapes.
+    int64_t pused = 0;
     for (int bo = 0; bo < nb; ++bo) {
       if (per_out[bo].empty()) continue;
       const PsiBlk& ob = O.blocks[bo];
+      int64_t kt = 0;
+      for (const GContrib& c : per_out[bo])
+        if (!(c.flags & GF_IDENT_A)) kt += (int64_t)c.nred * ((c.K + 31) / 32);
+      const int64_t nparts = std::max<int64_t>(1, (kt + opt.ksplit_tiles - 1) / opt.ksplit_tiles);
       lstep.begin(ob.dl, ob.dr, 1, 1, ob.off, ob.dr, 0, true);
-      for (auto& c : per_out[bo]) lstep.add(c);
+      for (const GContrib& c : per_out[bo])
+        if (c.flags & GF_IDENT_A) lstep.add(c);
+      const int64_t target = (kt + nparts - 1) / nparts, blk = (int64_t)ob.dl * ob.dr;
+      int64_t in_part = 0, part = 0;
+      for (const GContrib& c : per_out[bo]) {
+        if (c.flags & GF_IDENT_A) continue;
+        const int64_t per = (c.K + 31) / 32;
+        for (int m = 0; m < c.nred;) {
+          if (in_part >= target && part + 1 < nparts) {
+            lstep.end();
+            lstep.begin(ob.dl, ob.dr, 1, O.pbuf, pused + part * blk, ob.dr, 0, false);
+            lstep.tasks.back().accumulate |= GT_C64;
+            ++part;
+            in_part = 0;
+          }
+          const int take = (int)std::max<int64_t>(
+              1, std::min<int64_t>(c.nred - m, (target - in_part + per - 1) / per));
+          GContrib d = c;
+          d.nred = take;
+          d.a_off += (int64_t)m * c.a_rstride;
+          d.b_off += (int64_t)m * c.b_rstride;
+          d.s_off += (int64_t)m * c.s_rstride;
+          lstep.add(d);
+          in_part += take * per;
+          m += take;
+        }
+      }
       lstep.end();
+      if (part > 0) {
+        ReduceSeg r{};
+        r.dst_buf = 1;
+        r.src_buf = O.pbuf;
+        r.nsrc = (int32_t)part;
+        r.dst_off = ob.off;
+        r.src_off = pused;
+        r.src_stride = blk;
+        r.n = blk;
+        lstep.reduce.push_back(r);
+        pused += part * blk;
+      }
     }
+    partial_max = std::max(partial_max, pused);
     O.flops_r += rstep.flops;
     O.flops_l += lstep.flops;
     O.ngemm_r += rstep.ngemm;
     O.ngemm_l += lstep.ngemm;
   }
+  O.partial_bytes = (size_t)std::max<int64_t>(1, partial_max) * sizeof(double);
+  O.partial = (double*)dev_alloc(partial_max > 0 ? O.partial_bytes : 256);
+  tab.set(O.pbuf, O.partial);
   // launches: [L(identity) + R(0)], [L(0) + R(1)], ..., [L(n-2) + R(n-1)], [L(n-1)];
   // the L-step of one chunk shares a launch with the R-step of the next one
   // so that the short R-step jobs fill the tail of the long L-step jobs.
@@ -832,6 +888,10 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
       GemmList m = GemmList::merge_by_cost(parts);
       if (m.tasks.empty()) continue;
       for (const GTask& t : m.tasks) bufs.insert(t.c_buf);
+      for (const ReduceSeg& r : m.reduce) {
+        bufs.insert(r.dst_buf);
+        bufs.insert(r.src_buf);
+      }
       for (const GContrib& c : m.contribs) {
         if (!(c.flags & GF_IDENT_A)) bufs.insert(c.a_buf);
         bufs.insert(c.b_buf);
@@ -1151,6 +1211,10 @@ void make_reduced_copies(Ops& O, void* stream) {
     O.X32[sl] = (float*)dev_alloc(std::max<size_t>(256, O.Xbytes / 2));
     t32->set(O.Xbuf[sl], O.X32[sl]);
     need.erase(O.Xbuf[sl]);
+  }
+  if (need.count(O.pbuf)) {  // split-k partials are binary64 in every precision
+    t32->set(O.pbuf, O.partial);
+    need.erase(O.pbuf);
   }
   DMRG_CHECK(need.empty(), DMRG_EINTERNAL, "sigma plan reads a buffer without a reduced-precision copy");
   O.psi32 = (float*)dev_alloc(sizeof(float) * (size_t)O.npsi);

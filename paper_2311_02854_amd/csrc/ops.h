@@ -62,6 +62,11 @@ struct Ops {
   double* X[2] = {nullptr, nullptr};  // R-step scratch (two slots)
   int Xbuf[2] = {-1, -1};
   size_t Xbytes = 0;
+  // split-k partial outputs of the long L-step tasks of one launch (binary64
+  // in every precision), added into sigma at the end of that launch
+  double* partial = nullptr;
+  int pbuf = -1;
+  size_t partial_bytes = 0;
   // reduced precision (FP32 / BF16x3): FP32 copies of every buffer the plan
   // reads, under the same buffer ids in a second pointer table
   std::vector<int> sigma_bufs;        // buffer ids read or written by the sigma launches
@@ -110,6 +115,9 @@ struct Ops {
 struct BuildOptions {
   size_t x_budget = size_t(16) << 30;      // bytes of each R-step scratch slot (fewer, longer launches)
   size_t t_budget = size_t(2) << 30;       // bytes of renormalization scratch
+  // L-step tasks whose k loop exceeds this many k tiles (of 32) are split
+  // into about equal parts, run as separate jobs (split k)
+  int64_t ksplit_tiles = 512;
 };
 
 std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bond, const int* nsec,

@@ -8,7 +8,7 @@
 // device layer checks every launch's addressing; this program only drives it.
 //
 //   plancheck INPUT X_BUDGET_BYTES full|short [batched|noalloc_fails]
-// full: sigma with every launch shape; short: the 64x64 and mixed shapes with
+// full: sigma with every launch shape; short: the 64x64, mixed and big shapes with
 // one workgroup per job and dynamic units only (the other shapes share their
 // addressing code); batched: also the fused two-problem sigma; noalloc_fails:
 // dmrg_diag_noalloc must refuse (run with a static scratch set too small)
@@ -130,7 +130,9 @@ int main(int argc, char** argv) {
   dmrg_integrals I{K, h.data(), eri.data(), 0.0};
   dmrg_mps M{K, (int)hdr[1], (int)hdr[2], (int)hdr[3], nsec.data(), sec_qn.data(), sec_dim.data(),
              blk_off.data(), data.data()};
-  dmrg_build_opts bo{x_budget, 0};
+  // PLANCHECK_KSPLIT: split-k threshold of sigma's L-step (default when unset)
+  const char* ks = std::getenv("PLANCHECK_KSPLIT");
+  dmrg_build_opts bo{x_budget, 0, ks ? std::atoll(ks) : 0};
   dmrg_ops* ops = nullptr;
   ok(dmrg_build_ops(ctx, &I, &M, &bo, &ops), ctx, "build_ops");
   int64_t npsi = 0, nb = 0;
@@ -140,7 +142,8 @@ int main(int argc, char** argv) {
   for (int prec = 0; prec < 3; ++prec)
     for (int tile = 0; tile < dmrg::NTILE; ++tile)
       for (int64_t grid : {int64_t(0), int64_t(-1), int64_t(64)}) {
-        if (quick && ((tile != dmrg::TILE_64x64 && tile != dmrg::TILE_EDGE) || grid > 0)) continue;
+        if (quick && ((tile != dmrg::TILE_64x64 && tile != dmrg::TILE_EDGE && tile != dmrg::TILE_BIG) || grid > 0))
+          continue;
         ok(dmrg_launch_shape(ops, prec, tile, grid), ctx, "launch_shape");
         ok(dmrg_sigma(ctx, ops, psi, sig, prec), ctx, "sigma");
       }

@@ -33,7 +33,6 @@ namespace {
 constexpr uint64_t BASE = uint64_t(1) << 44;  // fake device addresses start here
 constexpr uint64_t GAP = uint64_t(1) << 20;   // unmapped bytes between allocations
 constexpr int64_t BKC = 32;                   // k tile of the GEMM kernel
-constexpr int NTC = 256;                      // threads per workgroup
 
 struct Alloc {
   uint64_t size;
@@ -129,6 +128,7 @@ void* dev_alloc_nozero(size_t bytes) { return dev_alloc(bytes); }
 void* host_alloc_pinned(size_t bytes) { return new char[bytes ? bytes : 1]; }
 void host_free_pinned(void* p) { delete[] (char*)p; }
 void dev_h2d_async(void* dst, const void* src, size_t bytes, void*) { dev_h2d(dst, src, bytes); }
+void dev_h2d_on(void* dst, const void* src, size_t bytes, void*) { dev_h2d(dst, src, bytes); }
 
 void dev_free(void* p) {
   if (!p) return;
@@ -211,6 +211,7 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
                  int64_t grid_per_xcd, void*) {
   if (ntasks == 0 || map.max_jobs == 0) return;
   if (tile < 0 || tile >= NTILE) fail("unknown tile shape");
+  if (tile == TILE_BIG) fail("TILE_BIG is split on the host into TILE_128 and TILE_EDGE launches");
   if (elem != P_F64 && elem != P_F32 && elem != P_BF16X3) fail("unknown precision");
   ++g_stats.launches;
   const int64_t tsz = elem == P_F64 ? 8 : 4;
@@ -277,7 +278,8 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
   for (int ti = 0; ti < ntasks; ++ti) {
     const GTask& t = T[ti];
     const int shape = tile == TILE_EDGE ? t.shape : tile;
-    if (shape < 0 || shape >= TILE_EDGE) fail("task shape invalid");
+    if (shape < 0 || (shape >= TILE_EDGE && shape != TILE_128) || (tile == TILE_128 && t.shape != TILE_128))
+      fail("task shape invalid");
     const int BM = tile_rows(shape), BN = tile_cols(shape);
     if (t.M <= 0 || t.N <= 0 || t.nbatch <= 0) fail("empty task in a device list");
     if (t.tiles_m != (t.M + BM - 1) / BM || t.tiles_n != (t.N + BN - 1) / BN) fail("tile counts mismatch");
@@ -344,6 +346,23 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
 }
 
 // ---- vector kernels: range checks only ---------------------------------------
+
+// split-k reduction: every segment's output and partial ranges (binary64)
+void reduce_launch(const ReduceSeg* segs_dev, int nseg, void* const* table_dev, void* p1, void*) {
+  if (nseg <= 0) return;
+  const ReduceSeg* R = view<ReduceSeg>(segs_dev, (size_t)nseg, "reduction segments");
+  const size_t ntab = count_of(table_dev, sizeof(void*));
+  const void* const* tab = view<void*>(table_dev, ntab, "pointer table");
+  for (int i = 0; i < nseg; ++i) {
+    const ReduceSeg& r = R[i];
+    if (r.n <= 0 || r.nsrc <= 0 || r.src_stride < r.n) fail("reduction segment empty or overlapping partials");
+    check(buf_ptr(tab, ntab, r.dst_buf, nullptr, p1, "reduction output"), r.dst_off * 8, (r.dst_off + r.n) * 8,
+          "reduction output");
+    const char* src = buf_ptr(tab, ntab, r.src_buf, nullptr, p1, "reduction partial");
+    for (int64_t s : {int64_t(0), int64_t(r.nsrc - 1)})
+      check(src, (r.src_off + s * r.src_stride) * 8, (r.src_off + s * r.src_stride + r.n) * 8, "reduction partial");
+  }
+}
 
 void k_fill(double* x, double, int64_t n, void*) { check(x, 0, n * 8, "k_fill"); }
 void k_zero_bytes(void* p, size_t bytes, void*) { check(p, 0, (int64_t)bytes, "k_zero_bytes"); }

@@ -119,11 +119,11 @@ def test_batched_new_output_buffers(ctx, probs):
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_every_launch_shape_gives_identical_sigma(ctx, probs, prec):
-    # 64x64, 32x32, 64x32, 32x64, mixed edge strips; one workgroup per job,
+    # 64x64, 32x32, 64x32, 32x64, mixed edge strips, 128x128, big; one workgroup per job,
     # persistent, dynamic units (test_gpu_fullsize repeats this on 241-row sectors)
     ints, mps, ops, x = probs[2]
     ref = single(ops, x, prec)
-    for tile in range(5):
+    for tile in range(7):
         for grid in (0, 64, -1):
             ops.launch_shape(prec, tile, grid)
             got = single(ops, x, prec)

@@ -164,12 +164,13 @@ def test_wide_sectors_vs_o2(ctx):
     assert max(b[4] for b in ds.blocks) > 128
     ops = ctx.build_ops(ints, mps, x_budget=1 << 20)
     s = gpu_sigma(ops, psi)
-    # every launch mode (uniform 64/32 tiles, mixed 64/32 strips) and grid
+    # every launch mode (uniform 64/32/128 tiles, mixed 64/32 strips, 128x128
+    # interiors with the rest mixed) and grid
     # gives the same sigma bit for bit: each output element accumulates the
     # same k sequence
     for prec in (0, 1, 2):
         ref = gpu_sigma(ops, psi, prec)
-        for tile in range(5):
+        for tile in range(7):
             for grid in (0, -1):
                 ops.launch_shape(prec, tile, grid)
                 got = gpu_sigma(ops, psi, prec)

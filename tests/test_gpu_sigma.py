@@ -84,6 +84,25 @@ def test_sigma_vs_renormalized_oracle(ctx, K, Na, Nb, D, k, seed):
     assert_close(s, blocks.TwoDotBlocks(ints, mps).sigma(psi), ops.blk_off, label=f"K{K} D{D}")
 
 
+@pytest.mark.parametrize("ksplit", [1, 3, 40])
+def test_split_k_sigma_vs_renormalized_oracle(ctx, ksplit):
+    # L-step tasks cut into parts of at most `ksplit` k tiles (one part per
+    # k tile at 1): the parts' partial blocks and the reduction that adds
+    # them into sigma, against O1, in every launch shape bit for bit
+    ints, mps, psi = problem(12, 6, 6, 200, 4, 6)
+    ops = ctx.build_ops(ints, mps, x_budget=1 << 20, ksplit_tiles=ksplit)
+    s = gpu_sigma(ops, psi)
+    assert_close(s, blocks.TwoDotBlocks(ints, mps).sigma(psi), ops.blk_off, label=f"ksplit {ksplit}")
+    for prec in (0, 1, 2):
+        ref = gpu_sigma(ops, psi, prec)
+        for tile in range(7):
+            for grid in (0, -1):
+                ops.launch_shape(prec, tile, grid)
+                got = gpu_sigma(ops, psi, prec)
+                assert np.array_equal(got, ref), (prec, tile, grid, np.abs(got - ref).max())
+        ops.launch_shape(prec, 0, 0)
+
+
 def test_sigma_with_core_energy(ctx):
     ints, mps, psi = problem(8, 4, 4, 32, 3, 7, ecore=3.7)
     ops = ctx.build_ops(ints, mps)

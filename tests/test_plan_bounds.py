@@ -13,6 +13,7 @@ the full-size coverage whose GPU half is test_gpu_fullsize.py.
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -28,14 +29,78 @@ PLANNER = ["blocks.cpp", "ops.cpp", "davidson.cpp", "decimate.cpp", "mlp.cpp", "
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
 
 
+CASES = {
+    # id: (K, N, D, seed, x_budget, mode, static scratch bytes or None); the
+    # longest runs first, so that writing the later inputs overlaps them.
+    # K14 also cuts its L-step into parts of at most 3 k tiles (split k).
+    "K14_D600": (14, 14, 600, 8, 4 << 20, ("full", "batched"), None),   # 241-row sectors, every launch shape, X chunks, fused plan
+    "K73_D2000": (73, 114, 2000, 5, 16 << 30, ("short",), None),        # config 5 (the benchmark bond), default scratch
+    "K36_D3000": (36, 36, 3000, 3, 16 << 30, ("short",), None),         # config 3
+    "K24_D1000": (24, 24, 1000, 2, 64 << 20, ("short",), None),         # config 2 sizes
+    # dmrg_diag_noalloc with a 5 MiB static scratch (K24 D1000: members in
+    # many chunks, no allocation, every launch in bounds) and with 4 MiB (its
+    # task-list reserve alone fills it: refused with DMRG_ENOMEM)
+    "noalloc_5MiB": (24, 24, 1000, 2, 64 << 20, ("short",), 5 << 20),
+    "noalloc_4MiB": (24, 24, 1000, 2, 64 << 20, ("short", "noalloc_fails"), 4 << 20),
+}
+
+
+def _env(scratch=None, ksplit=None):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    if scratch is not None:
+        env["PLANCHECK_SCRATCH_BYTES"] = str(scratch)
+    if ksplit is not None:
+        env["PLANCHECK_KSPLIT"] = str(ksplit)
+    return env
+
+
 @pytest.fixture(scope="module")
 def exe():
     os.makedirs(BUILD, exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in PLANNER] + [os.path.join(HERE, "stub_device.cpp"),
                                                         os.path.join(HERE, "driver.cpp")]
-    cmd = ["g++", "-O1", "-g", "-std=c++17", *SAN, *srcs, "-o", EXE]
-    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
+    # one compiler per source, in parallel, then one link
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        list(ex.map(lambda so: subprocess.run(["g++", "-O1", "-g", "-std=c++17", *SAN, "-c", so[0], "-o", so[1]],
+                                              check=True, capture_output=True, text=True), zip(srcs, objs)))
+    subprocess.run(["g++", *SAN, *objs, "-o", EXE], check=True, capture_output=True, text=True)
     return EXE
+
+
+@pytest.fixture(scope="module")
+def launched(exe, tmp_path_factory):
+    """Every case's checker run, started at once (they take 15-95 s each)."""
+    d = tmp_path_factory.mktemp("plans")
+    procs = {}
+    written = {}
+    for cid, (K, N, D, seed, xb, mode, scratch) in CASES.items():
+        key = (K, N, D, seed)
+        if key not in written:
+            written[key] = str(d / f"problem_{K}_{D}_{seed}.bin")
+            write_problem(written[key], K, N // 2, N // 2, D, K // 2 - 1, seed)
+        out = open(d / f"{cid}.out", "w+")
+        err = open(d / f"{cid}.err", "w+")
+        procs[cid] = (subprocess.Popen([exe, written[key], str(xb), *mode], stdout=out, stderr=err, text=True,
+                                       env=_env(scratch, 3 if cid == "K14_D600" else None)), out, err)
+    yield procs
+    for p, out, err in procs.values():
+        if p.poll() is None:
+            p.kill()
+            p.wait()
+        out.close()
+        err.close()
+
+
+def result(launched, cid):
+    p, out, err = launched[cid]
+    p.wait(timeout=1200)
+    out.seek(0)
+    err.seek(0)
+    r = subprocess.CompletedProcess(p.args, p.returncode, out.read(), err.read())
+    print(r.stdout[-2000:], r.stderr[-4000:])
+    return r
 
 
 def write_problem(path, K, Na, Nb, D, k, seed):
@@ -54,45 +119,23 @@ def write_problem(path, K, Na, Nb, D, k, seed):
         ints["eri"].astype(np.float64).tofile(f)
 
 
-def run(exe, *args, scratch=None):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
-               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    if scratch is not None:
-        env["PLANCHECK_SCRATCH_BYTES"] = str(scratch)
-    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=1200, env=env)
-    print(r.stdout[-2000:], r.stderr[-4000:])
-    return r
-
-
 def test_checker_refuses_bad_tasks(exe):
-    r = run(exe, "selftest")
+    r = subprocess.run([exe, "selftest"], capture_output=True, text=True, timeout=600, env=_env())
+    print(r.stdout[-2000:], r.stderr[-4000:])
     assert r.returncode == 0
     assert r.stdout.count("refused") == 2
 
 
-@pytest.mark.parametrize("K,N,D,seed,xbudget,mode", [
-    (14, 14, 600, 8, 4 << 20, ("full", "batched")),   # 241-row sectors, every launch shape, X chunks, fused plan
-    (24, 24, 1000, 2, 64 << 20, ("short",)),          # config 2 sizes
-    (36, 36, 3000, 3, 16 << 30, ("short",)),          # config 3
-    (73, 114, 2000, 5, 16 << 30, ("short",)),         # config 5 (the benchmark bond), default scratch
-], ids=["K14_D600", "K24_D1000", "K36_D3000", "K73_D2000"])
-def test_full_size_plans_stay_in_bounds(exe, tmp_path, K, N, D, seed, xbudget, mode):
-    path = str(tmp_path / "problem.bin")
-    write_problem(path, K, N // 2, N // 2, D, K // 2 - 1, seed)
-    r = run(exe, path, str(xbudget), *mode)
+@pytest.mark.parametrize("cid", ["K14_D600", "K24_D1000", "K36_D3000", "K73_D2000"])
+def test_full_size_plans_stay_in_bounds(launched, cid):
+    r = result(launched, cid)
     assert r.returncode == 0, r.stderr[-4000:]
     assert "PLANCHECK OK" in r.stdout
 
 
-@pytest.mark.parametrize("scratch,expect", [(5 << 20, "ok"), (4 << 20, "refused")])
-def test_diag_noalloc_chunks_and_limit(exe, tmp_path, scratch, expect):
-    # dmrg_diag_noalloc with a 5 MiB static scratch (K24 D1000: members in
-    # many chunks, no allocation, every launch in bounds) and with 4 MiB (its
-    # task-list reserve alone fills it: refused with DMRG_ENOMEM)
-    path = str(tmp_path / "problem.bin")
-    write_problem(path, 24, 12, 12, 1000, 11, 2)
-    mode = ("short",) if expect == "ok" else ("short", "noalloc_fails")
-    r = run(exe, path, str(64 << 20), *mode, scratch=scratch)
+@pytest.mark.parametrize("cid,expect", [("noalloc_5MiB", "ok"), ("noalloc_4MiB", "refused")])
+def test_diag_noalloc_chunks_and_limit(launched, cid, expect):
+    r = result(launched, cid)
     assert r.returncode == 0, r.stderr[-4000:]
     assert "PLANCHECK OK" in r.stdout
     if expect == "refused":
