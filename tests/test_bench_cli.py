@@ -7,6 +7,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
@@ -27,20 +29,22 @@ def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     sha = hashlib.sha256(src.read_bytes()).hexdigest()
     prof.write_text(f"# counters\n\n- kernel_source_sha256: `{sha}`\n- hbm_bytes_per_call: `2.5e+12`\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", {"fp64": str(prof), "bf16x3": str(tmp_path / "none.md")})
     assert bench.measured_traffic("5", "fp64") == 2.5e12
-    # other workloads and precisions have no committed counters
+    # other workloads, and precisions without a summary, have no traffic
     assert bench.measured_traffic("2", "fp64") is None
     assert bench.measured_traffic("5", "bf16x3") is None
+    assert bench.measured_traffic("5", "fp32") is None
     # a changed kernel makes the stored traffic stale
     src.write_text("// kernel v2\n")
     assert bench.measured_traffic("5", "fp64") is None
 
 
-def test_committed_profile_is_well_formed():
+@pytest.mark.parametrize("prec,algo", [("fp64", 0.49e12), ("fp32", 0.25e12), ("bf16x3", 0.25e12)])
+def test_committed_profile_is_well_formed(prec, algo):
     import bench
-    text = open(bench.TRAFFIC_PROFILE).read()
+    text = open(bench.TRAFFIC_PROFILE[prec]).read()
     assert "kernel_source_sha256:" in text and "hbm_bytes_per_call:" in text
-    v = bench.measured_traffic("5", "fp64")
-    # null when the kernel changed since the counters; else at least the algorithmic 0.49 TB
-    assert v is None or 0.49e12 < v < 2e13
+    v = bench.measured_traffic("5", prec)
+    # null when the kernel changed since the counters; else at least the algorithmic bytes
+    assert v is None or algo < v < 2e13
