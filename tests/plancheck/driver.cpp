@@ -3,14 +3,15 @@
 // Reads one two-dot problem written by tests/test_plan_bounds.py, builds its
 // operators through the C ABI on the dry-run device layer (stub_device.cpp),
 // then issues sigma in every precision with every launch shape (each tile
-// shape, one workgroup per job, persistent and dynamic grids), diag(H) and,
+// shape, one workgroup per job and dynamic units), diag(H) and,
 // with a second copy of the problem, the fused two-problem sigma.  The
 // device layer checks every launch's addressing; this program only drives it.
 //
 //   plancheck INPUT X_BUDGET_BYTES full|short [batched|noalloc_fails]
-// full: sigma with every launch shape; short: the 64x64, mixed and big shapes with
-// one workgroup per job and dynamic units only (the other shapes share their
-// addressing code); batched: also the fused two-problem sigma; noalloc_fails:
+// full: sigma with every launch shape, one workgroup per job and dynamic units
+// (a persistent grid only strides the same jobs); short: the 64x64, mixed and
+// big shapes only (the other shapes share their addressing code); batched: also
+// the fused two-problem sigma; noalloc_fails:
 // dmrg_diag_noalloc must refuse (run with a static scratch set too small)
 #include <cstdio>
 #include <cstdlib>
@@ -141,8 +142,8 @@ int main(int argc, char** argv) {
   double* sig = (double*)dmrg::dev_alloc(sizeof(double) * (size_t)npsi);
   for (int prec = 0; prec < 3; ++prec)
     for (int tile = 0; tile < dmrg::NTILE; ++tile)
-      for (int64_t grid : {int64_t(0), int64_t(-1), int64_t(64)}) {
-        if (quick && ((tile != dmrg::TILE_64x64 && tile != dmrg::TILE_EDGE && tile != dmrg::TILE_BIG) || grid > 0))
+      for (int64_t grid : {int64_t(0), int64_t(-1)}) {
+        if (quick && tile != dmrg::TILE_64x64 && tile != dmrg::TILE_EDGE && tile != dmrg::TILE_BIG)
           continue;
         ok(dmrg_launch_shape(ops, prec, tile, grid), ctx, "launch_shape");
         ok(dmrg_sigma(ctx, ops, psi, sig, prec), ctx, "sigma");
