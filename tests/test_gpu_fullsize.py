@@ -93,6 +93,15 @@ def test_number_shift_full_size(ctx, K, N, D, seed):
         e[i] = 1.0
         hii = gpu_sigma(ops, e)[i]
         assert abs(dg[i] - hii) <= 1e-12 * max(1.0, abs(hii)), (i, dg[i], hii)
+    # the launch modes the autotuner picks at these sizes (mixed strips with
+    # dynamic units; 128x128 interiors on 1024-thread workgroups) give the
+    # same sigma bit for bit
+    for tile, grid in ((4, -1), (6, 0), (6, -1)):
+        print(f"K={K} launch mode tile={tile} grid={grid}", flush=True)
+        ops.launch_shape(0, tile, grid)
+        got = gpu_sigma(ops, psi)
+        assert np.array_equal(got, s), (tile, grid, np.abs(got - s).max())
+    ops.launch_shape(0, 0, 0)
     release(ops)
     ops2 = ctx.build_ops(shifted, mps, x_budget=X_BUDGET)
     s2 = gpu_sigma(ops2, psi)
