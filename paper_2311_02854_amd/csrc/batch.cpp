@@ -121,6 +121,7 @@ void BatchPlan::issue(void* s, const std::vector<int>& tl, const std::vector<int
   for (size_t p = 0; p < probs.size(); ++p) {
     k_fill(sig_cur[p], 0.0, probs[p]->npsi, s);
     if (prec != P_F64) k_d2f(psi_cur[p], probs[p]->psi32, probs[p]->npsi, s);
+    gather_psi(*probs[p], psi_cur[p], prec, s);
   }
   if (ms) {
     while (events.size() < launches.size() + 1) events.push_back(ev_create());

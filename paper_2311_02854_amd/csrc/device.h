@@ -156,6 +156,9 @@ void graph_destroy(void* exec);
 void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GContrib* contribs_dev,
                  const int* bucket_dev, void* const* table_dev, const void* p0, void* p1, int elem, int tile,
                  int64_t grid_per_xcd, void* stream);
+// dst[d + e] = src[s + e] for every triplet (s, d, n) of seg_dev (device
+// memory, nseg triplets) and e < n; the destinations must not overlap.
+void k_copy_segments(const double* src, double* dst, const int64_t* seg_dev, int nseg, void* stream);
 // The segments segs_dev[0 .. nseg) of a split-k reduction (device memory),
 // in one launch; segments must not write the same elements.
 void reduce_launch(const ReduceSeg* segs_dev, int nseg, void* const* table_dev, void* p1, void* stream);

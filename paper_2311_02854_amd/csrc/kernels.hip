@@ -954,6 +954,18 @@ __global__ void reduce_kernel(const ReduceSeg* __restrict__ segs, void* const* _
   }
 }
 
+__global__ void copy_segments_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                     const int64_t* __restrict__ seg) {
+  const int64_t s = seg[3 * blockIdx.x], d = seg[3 * blockIdx.x + 1], n = seg[3 * blockIdx.x + 2];
+  for (int64_t e = (int64_t)blockIdx.y * 256 + threadIdx.x; e < n; e += 256 * (int64_t)gridDim.y) dst[d + e] = src[s + e];
+}
+
+void k_copy_segments(const double* src, double* dst, const int64_t* seg_dev, int nseg, void* stream) {
+  if (nseg <= 0) return;
+  hipLaunchKernelGGL(copy_segments_kernel, dim3((unsigned)nseg, 8), dim3(256), 0, S(stream), src, dst, seg_dev);
+  dev_check("k_copy_segments");
+}
+
 void reduce_launch(const ReduceSeg* segs_dev, int nseg, void* const* table_dev, void* p1, void* stream) {
   if (nseg <= 0) return;
   hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)nseg, 8), dim3(256), 0, S(stream), segs_dev, table_dev,

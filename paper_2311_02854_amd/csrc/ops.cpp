@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <numeric>
 #include <cmath>
 #include <map>
 #include <set>
@@ -102,6 +103,9 @@ Ops::~Ops() {
   dev_free(X[0]);
   dev_free(X[1]);
   dev_free(partial);
+  dev_free(perm_seg);
+  dev_free(psi_perm);
+  dev_free(psi_perm32);
   dev_free(X32[0]);
   dev_free(X32[1]);
   dev_free(psi32);
@@ -672,8 +676,29 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
       if (!hv.empty() && r.xoff[bi] < 0) r.xoff[bi] = 0;
     }
   }
+  // psi blocks grouped by right sector (then block order): the R-step reads
+  // psi from this permuted copy, so that the blocks one R operator block
+  // multiplies stack into one tall operand (Eq. sigmablk56 for all of them at
+  // once: same K and the same right factor), with far fewer partial tiles
+  O.permbuf = tab.add(nullptr);
+  std::vector<int> perm(nb);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return O.blocks[a].ir < O.blocks[b].ir; });
+  std::vector<int> perm_pos(nb);
+  O.perm_off.assign(nb, 0);
+  {
+    int64_t off = 0;
+    for (int i = 0; i < nb; ++i) {
+      perm_pos[perm[i]] = i;
+      O.perm_off[perm[i]] = off;
+      off += (int64_t)O.blocks[perm[i]].dl * O.blocks[perm[i]].dr;
+    }
+  }
   for (auto& r : rs) {
-    for (int bi = 0; bi < nb; ++bi) {
+    // X blocks in the permuted order too, so that a run of stacked psi blocks
+    // writes one stacked X (rows of the run, leading dimension d_R')
+    for (int i = 0; i < nb; ++i) {
+      const int bi = perm[i];
       if (r.xoff[bi] < 0) continue;
       int ir2 = -1;
       eff(r.g, r.t, O.blocks[bi].ir, &ir2);
@@ -741,17 +766,27 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
       if (pc.src < 0) continue;
       const RSrc& r = rs[pc.src];
       const Layout& rl = r.g->lay;
-      for (int bi : r.need) {
-        const PsiBlk& b = O.blocks[bi];
+      // runs of needed blocks that are neighbours in the permuted psi (same
+      // right sector): one task each, its rows the blocks' rows stacked
+      for (size_t j0 = 0; j0 < r.need.size();) {
+        const PsiBlk& b = O.blocks[r.need[j0]];
+        size_t j1 = j0 + 1;
+        int rows = b.dl;
+        while (j1 < r.need.size() && O.blocks[r.need[j1]].ir == b.ir &&
+               perm_pos[r.need[j1]] == perm_pos[r.need[j1 - 1]] + 1) {
+          rows += O.blocks[r.need[j1]].dl;
+          ++j1;
+        }
         int ir2 = -1;
         int sb = eff(r.g, r.t, b.ir, &ir2);
         const int dr2 = O.Rb.dim[ir2];
-        rstep.begin(b.dl, dr2, pc.t1 - pc.t0, xb, pc.xbase + r.xoff[bi], dr2, r.stride, false);
-        GContrib c = make_contrib(b.dr, r.t ? 0 : GF_TRANS_B, 0, b.off, b.dr, r.g->buf,
+        rstep.begin(rows, dr2, pc.t1 - pc.t0, xb, pc.xbase + r.xoff[r.need[j0]], dr2, r.stride, false);
+        GContrib c = make_contrib(b.dr, r.t ? 0 : GF_TRANS_B, O.permbuf, O.perm_off[r.need[j0]], b.dr, r.g->buf,
                                   (int64_t)(r.base + pc.t0) * r.g->stride() + rl.off[sb], r.t ? dr2 : b.dr, 1.0);
         c.b_bstride = r.g->stride();
         rstep.add(c);
         rstep.end();
+        j0 = j1;
       }
     }
     // L-step: contributions grouped by output block
@@ -868,6 +903,18 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
     O.ngemm_r += rstep.ngemm;
     O.ngemm_l += lstep.ngemm;
   }
+  {
+    std::vector<int64_t> seg;
+    for (int bi = 0; bi < nb; ++bi) {
+      seg.push_back(O.blocks[bi].off);
+      seg.push_back(O.perm_off[bi]);
+      seg.push_back((int64_t)O.blocks[bi].dl * O.blocks[bi].dr);
+    }
+    O.perm_seg = (int64_t*)dev_alloc(sizeof(int64_t) * std::max<size_t>(3, seg.size()));
+    if (!seg.empty()) dev_h2d(O.perm_seg, seg.data(), sizeof(int64_t) * seg.size());
+    O.psi_perm = (double*)dev_alloc(sizeof(double) * (size_t)std::max<int64_t>(1, O.npsi));
+    tab.set(O.permbuf, O.psi_perm);
+  }
   O.partial_bytes = (size_t)std::max<int64_t>(1, partial_max) * sizeof(double);
   O.partial = (double*)dev_alloc(partial_max > 0 ? O.partial_bytes : 256);
   tab.set(O.pbuf, O.partial);
@@ -916,6 +963,11 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
 }
 
 // ----------------------------------------------------------------------------
+void gather_psi(Ops& O, const double* psi, int prec, void* stream) {
+  k_copy_segments(psi, O.psi_perm, O.perm_seg, (int)O.blocks.size(), stream);
+  if (prec != P_F64) k_d2f(O.psi_perm, O.psi_perm32, O.npsi, stream);
+}
+
 void sigma_run(Ops& O, const double* psi, double* sigma, int prec, void* stream) {
   DMRG_CHECK(prec == P_F64 || prec == P_F32 || prec == P_BF16X3, DMRG_EINVAL, "unknown precision");
   DevTable* tab = O.tab.get();
@@ -933,6 +985,7 @@ void sigma_run(Ops& O, const double* psi, double* sigma, int prec, void* stream)
     l.run_tile(tuned ? O.tile_choice[prec][i] : TILE_64x64, *tab, p0, sigma, prec, stream);
   };
   k_fill(sigma, 0.0, O.npsi, stream);
+  gather_psi(O, psi, prec, stream);
   if (!O.profile) {
     for (size_t i = 0; i < O.launches.size(); ++i) launch(i);
     return;
@@ -996,6 +1049,7 @@ void sigma_autotune(Ops& O, int prec, void* stream) {
     tab = O.tab32.get();
     p0 = O.psi32;
   }
+  gather_psi(O, psi, prec, stream);
   while (O.events.size() < nl + 1) O.events.push_back(ev_create());
   auto run_all = [&](const std::vector<int>& tiles, const std::vector<int64_t>& grids, std::vector<double>& ms) {
     k_fill(sig, 0.0, O.npsi, stream);
@@ -1211,6 +1265,11 @@ void make_reduced_copies(Ops& O, void* stream) {
     O.X32[sl] = (float*)dev_alloc(std::max<size_t>(256, O.Xbytes / 2));
     t32->set(O.Xbuf[sl], O.X32[sl]);
     need.erase(O.Xbuf[sl]);
+  }
+  if (need.count(O.permbuf)) {
+    O.psi_perm32 = (float*)dev_alloc(sizeof(float) * (size_t)std::max<int64_t>(1, O.npsi));
+    t32->set(O.permbuf, O.psi_perm32);
+    need.erase(O.permbuf);
   }
   if (need.count(O.pbuf)) {  // split-k partials are binary64 in every precision
     t32->set(O.pbuf, O.partial);

@@ -67,6 +67,12 @@ struct Ops {
   double* partial = nullptr;
   int pbuf = -1;
   size_t partial_bytes = 0;
+  // psi with its blocks grouped by right sector: the R-step's operand
+  std::vector<int64_t> perm_off;      // per block: its offset there
+  int64_t* perm_seg = nullptr;        // device (src, dst, count) triplets of the gather
+  double* psi_perm = nullptr;
+  float* psi_perm32 = nullptr;
+  int permbuf = -1;
   // reduced precision (FP32 / BF16x3): FP32 copies of every buffer the plan
   // reads, under the same buffer ids in a second pointer table
   std::vector<int> sigma_bufs;        // buffer ids read or written by the sigma launches
@@ -125,6 +131,9 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
                                const double* data, void* stream, const BuildOptions& opt);
 
 void sigma_run(Ops& ops, const double* psi, double* sigma, int prec, void* stream);
+// Copy psi into ops.psi_perm (its blocks grouped by right sector; and into
+// ops.psi_perm32 for a reduced precision) before the sigma launches.
+void gather_psi(Ops& ops, const double* psi, int prec, void* stream);
 // Time every tile shape (then a persistent grid) on every launch of one sigma
 // call in precision prec and keep the fastest per launch.  Synchronous.
 void sigma_autotune(Ops& ops, int prec, void* stream);

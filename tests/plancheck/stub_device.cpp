@@ -347,6 +347,16 @@ void gemm_launch(const GTask* tasks_dev, int ntasks, const XcdMap& map, const GC
 
 // ---- vector kernels: range checks only ---------------------------------------
 
+void k_copy_segments(const double* src, double* dst, const int64_t* seg_dev, int nseg, void*) {
+  if (nseg <= 0) return;
+  const int64_t* S = view<int64_t>(seg_dev, 3 * (size_t)nseg, "copy segments");
+  for (int i = 0; i < nseg; ++i) {
+    if (S[3 * i + 2] <= 0) fail("empty copy segment");
+    check(src, S[3 * i] * 8, (S[3 * i] + S[3 * i + 2]) * 8, "copy source");
+    check(dst, S[3 * i + 1] * 8, (S[3 * i + 1] + S[3 * i + 2]) * 8, "copy destination");
+  }
+}
+
 // split-k reduction: every segment's output and partial ranges (binary64)
 void reduce_launch(const ReduceSeg* segs_dev, int nseg, void* const* table_dev, void* p1, void*) {
   if (nseg <= 0) return;
