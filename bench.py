@@ -391,6 +391,8 @@ def main():
                     help="skip the Davidson time-to-1e-6 Eh leg (plain FP64 + diagonal vs shifted, split-BF16, learned)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured DGEMM / copy / batched peaks")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep leg of --config 2")
+    ap.add_argument("--ksplit", type=int, default=0,
+                    help="split-k threshold of the L-step in k tiles (0: the library default, 512)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 64-problem fused-launch leg of the default run")
     ap.add_argument("--build-only", action="store_true",
@@ -424,7 +426,7 @@ def main():
     log(f"[bench] synthetic inputs {time.time() - t0:.1f} s, n_psi={len(psi)}")
     ctx = gpu_context(0)
     t0 = time.time()
-    ops = ctx.build_ops(ints, mps, x_budget=int(args.x_budget_gb * 1e9))
+    ops = ctx.build_ops(ints, mps, x_budget=int(args.x_budget_gb * 1e9), ksplit_tiles=args.ksplit)
     t_build = time.time() - t0
     st = ops.stats()
     log(f"[bench] build_ops {t_build:.1f} s ({st['build_flops'] / 1e12:.1f} TFLOP renormalization), "
