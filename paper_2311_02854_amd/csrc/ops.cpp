@@ -871,8 +871,11 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
             ++part;
             in_part = 0;
           }
-          const int take = (int)std::max<int64_t>(
-              1, std::min<int64_t>(c.nred - m, (target - in_part + per - 1) / per));
+          // the last part takes every member left in one piece
+          const int take = part + 1 >= nparts
+                               ? c.nred - m
+                               : (int)std::max<int64_t>(
+                                     1, std::min<int64_t>(c.nred - m, (target - in_part + per - 1) / per));
           GContrib d = c;
           d.nred = take;
           d.a_off += (int64_t)m * c.a_rstride;
@@ -906,10 +909,13 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
   {
     std::vector<int64_t> seg;
     for (int bi = 0; bi < nb; ++bi) {
+      const int64_t n = (int64_t)O.blocks[bi].dl * O.blocks[bi].dr;
+      if (n == 0) continue;
       seg.push_back(O.blocks[bi].off);
       seg.push_back(O.perm_off[bi]);
-      seg.push_back((int64_t)O.blocks[bi].dl * O.blocks[bi].dr);
+      seg.push_back(n);
     }
+    O.nperm_seg = (int)(seg.size() / 3);
     O.perm_seg = (int64_t*)dev_alloc(sizeof(int64_t) * std::max<size_t>(3, seg.size()));
     if (!seg.empty()) dev_h2d(O.perm_seg, seg.data(), sizeof(int64_t) * seg.size());
     O.psi_perm = (double*)dev_alloc(sizeof(double) * (size_t)std::max<int64_t>(1, O.npsi));
@@ -964,7 +970,7 @@ std::unique_ptr<Ops> build_ops(const Integrals& I, int K, int Na, int Nb, int bo
 
 // ----------------------------------------------------------------------------
 void gather_psi(Ops& O, const double* psi, int prec, void* stream) {
-  k_copy_segments(psi, O.psi_perm, O.perm_seg, (int)O.blocks.size(), stream);
+  k_copy_segments(psi, O.psi_perm, O.perm_seg, O.nperm_seg, stream);
   if (prec != P_F64) k_d2f(O.psi_perm, O.psi_perm32, O.npsi, stream);
 }
 

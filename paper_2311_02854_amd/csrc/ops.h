@@ -70,6 +70,7 @@ struct Ops {
   // psi with its blocks grouped by right sector: the R-step's operand
   std::vector<int64_t> perm_off;      // per block: its offset there
   int64_t* perm_seg = nullptr;        // device (src, dst, count) triplets of the gather
+  int nperm_seg = 0;
   double* psi_perm = nullptr;
   float* psi_perm32 = nullptr;
   int permbuf = -1;
