@@ -180,7 +180,9 @@ int dmrg_build_ops(dmrg_ctx* ctx, const dmrg_integrals* ints, const dmrg_mps* mp
                    const dmrg_build_opts* opts, dmrg_ops** out);
 void dmrg_ops_destroy(dmrg_ops* ops);
 
-/* psi layout: blocks (il, n1, n2, ir), il a sector of bond `bond`, ir the sector
+/* psi layout: the symmetry blocks of the two-dot wavefunction Psi^{l c1 c2 r}
+ * (Eq. Sigma; stored blockwise as in Sec. 2.2, where each block is a matrix in
+ * C order): blocks (il, n1, n2, ir), il a sector of bond `bond`, ir the sector
  * of bond `bond+2` with q(ir) = q(il) + q(n1) + q(n2), enumerated by (il, n1, n2);
  * each block d_il x d_ir row-major.  blk_meta[6*nb] = (il, n1, n2, ir, d_il, d_ir),
  * blk_off[nb] = element offsets.  Either array may be NULL. */
@@ -201,7 +203,12 @@ int dmrg_profile(dmrg_ops* ops, int enable);
 int dmrg_sigma(dmrg_ctx* ctx, dmrg_ops* ops, const double* psi, double* sigma,
                int precision);
 
-/* Diagonal H_ii of the two-dot Hamiltonian in the psi layout (device output). */
+/* Diagonal H_ii of the two-dot Hamiltonian of Eq. Sigma in the psi layout
+ * (device output): the Davidson preconditioner's diagonal (the diagonal part
+ * of the Hamiltonian that Sec. 3 lists among the steps outside sigma).  It
+ * sums the terms of Eq. totoalH whose operators conserve every block's
+ * quantum numbers, from the diagonals of their renormalized operators.
+ * Synchronous. */
 int dmrg_diag(dmrg_ctx* ctx, dmrg_ops* ops, double* diag);
 
 /* dmrg_diag for callers that cannot allocate device memory (code under HIP
