@@ -1159,6 +1159,7 @@ void diag_run(Ops& O, double* diag, void* stream) {
     dev_free(dL);
     dev_free(dR);
   }
+  dev_sync(stream);  // also when no family contributes (the fill above)
 }
 
 // The same sum as diag_run, for callers that cannot allocate: the members of
