@@ -130,18 +130,20 @@ def log(*a):
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2311_02854_amd", "csrc", "kernels.hip")
-TRAFFIC_PROFILE = {prec: os.path.join(ROOT, "profiles", f"gemm_kernel_{tag}_sigma_K73_D2000_pmc.md")
+# committed rocprofv3 counter summaries, by (workload, precision)
+TRAFFIC_PROFILE = {("5", prec): os.path.join(ROOT, "profiles", f"gemm_kernel_{tag}_sigma_K73_D2000_pmc.md")
                    for prec, tag in (("fp64", "f64"), ("fp32", "f32"), ("bf16x3", "bf16x3"))}
+TRAFFIC_PROFILE[("3", "fp64")] = os.path.join(ROOT, "profiles", "gemm_kernel_f64_sigma_K36_D3000_pmc.md")
 
 
 def measured_traffic(config, precision):
     """HBM bytes per sigma call from the committed rocprofv3 PMC summary of
-    this precision (FETCH_SIZE x fetch factor + WRITE_SIZE x write factor,
-    KiB -> bytes), or None if there is none for this workload or the GEMM
+    this workload and precision (FETCH_SIZE x fetch factor + WRITE_SIZE x
+    write factor, KiB -> bytes), or None if there is none for them or the GEMM
     kernel source changed since the counters were taken."""
     import hashlib
-    path = TRAFFIC_PROFILE.get(precision)
-    if config != "5" or path is None or not os.path.exists(path):
+    path = TRAFFIC_PROFILE.get((config, precision))
+    if path is None or not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):

@@ -29,7 +29,7 @@ def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     sha = hashlib.sha256(src.read_bytes()).hexdigest()
     prof.write_text(f"# counters\n\n- kernel_source_sha256: `{sha}`\n- hbm_bytes_per_call: `2.5e+12`\n")
     monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
-    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", {"fp64": str(prof), "bf16x3": str(tmp_path / "none.md")})
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", {("5", "fp64"): str(prof), ("5", "bf16x3"): str(tmp_path / "none.md")})
     assert bench.measured_traffic("5", "fp64") == 2.5e12
     # other workloads, and precisions without a summary, have no traffic
     assert bench.measured_traffic("2", "fp64") is None
@@ -40,11 +40,12 @@ def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("5", "fp64") is None
 
 
-@pytest.mark.parametrize("prec,algo", [("fp64", 0.49e12), ("fp32", 0.25e12), ("bf16x3", 0.25e12)])
-def test_committed_profile_is_well_formed(prec, algo):
+@pytest.mark.parametrize("config,prec,algo", [("5", "fp64", 0.49e12), ("5", "fp32", 0.25e12),
+                                               ("5", "bf16x3", 0.25e12), ("3", "fp64", 0.31e12)])
+def test_committed_profile_is_well_formed(config, prec, algo):
     import bench
-    text = open(bench.TRAFFIC_PROFILE[prec]).read()
+    text = open(bench.TRAFFIC_PROFILE[(config, prec)]).read()
     assert "kernel_source_sha256:" in text and "hbm_bytes_per_call:" in text
-    v = bench.measured_traffic("5", prec)
+    v = bench.measured_traffic(config, prec)
     # null when the kernel changed since the counters; else at least the algorithmic bytes
     assert v is None or algo < v < 2e13
