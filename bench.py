@@ -133,7 +133,8 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2311_02854_amd", "csrc", "kernels.hip")
 # committed rocprofv3 counter summaries, by (workload, precision)
 TRAFFIC_PROFILE = {("5", prec): os.path.join(ROOT, "profiles", f"gemm_kernel_{tag}_sigma_K73_D2000_pmc.md")
                    for prec, tag in (("fp64", "f64"), ("fp32", "f32"), ("bf16x3", "bf16x3"))}
-TRAFFIC_PROFILE[("3", "fp64")] = os.path.join(ROOT, "profiles", "gemm_kernel_f64_sigma_K36_D3000_pmc.md")
+TRAFFIC_PROFILE.update({("3", prec): os.path.join(ROOT, "profiles", f"gemm_kernel_{tag}_sigma_K36_D3000_pmc.md")
+                        for prec, tag in (("fp64", "f64"), ("fp32", "f32"), ("bf16x3", "bf16x3"))})
 
 
 def measured_traffic(config, precision):
@@ -404,7 +405,8 @@ def main():
     ap.add_argument("--build-only", action="store_true",
                     help="only build the operators (dmrg_build_ops) and print its wall time (for profiling)")
     ap.add_argument("--mixed", action="store_true",
-                    help="also report FP32 / split-BF16 sigma and energy errors (always on for --config 3)")
+                    help="also report FP32 / split-BF16 sigma and energy errors (on by default for --config 3)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg of --config 3")
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2311_02854_amd", "data", "precond_mlp.npy"),
                     help="learned preconditioner weights for --davidson")
     ap.add_argument("--copy-probe", action="store_true",
@@ -506,7 +508,7 @@ def main():
         log(f"[bench] measured peaks: {out['roofline']['measured_peaks']}")
     if args.config == "2" and not args.no_sweep:
         out["sweep"] = sweep_leg(ctx, ints, K, Na, Nb, D, seed)
-    if args.config == "3" or args.mixed:
+    if (args.config == "3" and not args.no_mixed) or args.mixed:
         out["mixed_precision"] = mixed_leg(ops, psi)
     if args.config == "5" and not args.no_davidson:
         out["davidson"] = davidson_leg(ops, psi, args.mlp)

@@ -41,7 +41,8 @@ def test_measured_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("config,prec,algo", [("5", "fp64", 0.49e12), ("5", "fp32", 0.25e12),
-                                               ("5", "bf16x3", 0.25e12), ("3", "fp64", 0.31e12)])
+                                               ("5", "bf16x3", 0.25e12), ("3", "fp64", 0.31e12),
+                                               ("3", "fp32", 0.16e12), ("3", "bf16x3", 0.16e12)])
 def test_committed_profile_is_well_formed(config, prec, algo):
     import bench
     text = open(bench.TRAFFIC_PROFILE[(config, prec)]).read()
