@@ -2,7 +2,7 @@
 accumulation) against the FP64 oracle, and the mixed-precision Davidson.
 
 Parity of reduced precision is not pinned by the paper (it has no such
-numbers); the FP64 oracle is the judge.  Tolerances (relative 2-norm of the
+numbers); the FP64 oracle is the reference.  Tolerances (relative 2-norm of the
 sigma error) follow from the unit roundoff of each format:
   FP32    u = 2^-24 ~ 6e-8: operands rounded once (|d| <= u) and FP32
           accumulation over n products gives a relative error ~ sqrt(n) u for
